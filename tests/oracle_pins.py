@@ -1,0 +1,269 @@
+"""Pins that tie the CPU oracle to the paper and to mathematics, not to itself.
+
+Each pin takes an ``oracle.Oracle`` and raises AssertionError on a mismatch, so
+the same battery runs against the real oracle (``test_oracle.py``) and against
+builds with a planted mistake (which must fail at least one pin).
+
+Sources of truth used here (none of them calls the oracle twice to agree with
+itself):
+  * hand-derived values from the Definition of included/excluded sums (Sec. 2);
+  * closed forms (all-ones and one-hot tensors);
+  * textbook routines written independently in numpy: the summed-area table
+    (Sec. 1, "Summed-area Table for Weak Excluded Sums") for +, a sliding
+    window maximum on an identity-padded array for max, numpy masks over the
+    complement of each box for excluded sums;
+  * invariants: with + on integers, included plus excluded equals the total;
+    with max, the larger of the two equals the global maximum; the 1-D
+    excluded sum is prefix(x-1) op suffix(x+k); permuting axes permutes the
+    result; k = n leaves an empty complement at the origin.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+from numpy.lib.stride_tricks import sliding_window_view
+
+I32_MIN = np.iinfo(np.int32).min
+I64_MIN = np.iinfo(np.int64).min
+
+
+def _ident(op, dtype):
+    if op == "sum":
+        return 0
+    return -np.inf if dtype in ("f32", "f64") else (I32_MIN if dtype == "i32" else I64_MIN)
+
+
+# --------------------------------------------------------------------------
+# hand-derived cases (from the Definition, Sec. 2)
+# --------------------------------------------------------------------------
+
+def pin_hand_1d(o):
+    # A = 1..8, k = 4 (the shape of the 1-D example of Sec. 3, whose figure
+    # values are not available; derived here by hand from the definition).
+    a = np.arange(1, 9)
+    inc_sum = [1 + 2 + 3 + 4, 2 + 3 + 4 + 5, 3 + 4 + 5 + 6, 4 + 5 + 6 + 7, 5 + 6 + 7 + 8,
+               6 + 7 + 8, 7 + 8, 8]
+    exc_sum = [5 + 6 + 7 + 8, 1 + 6 + 7 + 8, 1 + 2 + 7 + 8, 1 + 2 + 3 + 8, 1 + 2 + 3 + 4,
+               1 + 2 + 3 + 4 + 5, 1 + 2 + 3 + 4 + 5 + 6, 1 + 2 + 3 + 4 + 5 + 6 + 7]
+    inc_max = [4, 5, 6, 7, 8, 8, 8, 8]
+    exc_max = [8, 8, 8, 8, 4, 5, 6, 7]
+    for fn in ("brute", "scale"):
+        for dt in ("i64", "i32", "f64", "f32"):
+            i, e = getattr(o, fn)(a, [4], "sum", dt)
+            assert np.array_equal(i, inc_sum) and np.array_equal(e, exc_sum), (fn, dt, i, e)
+            i, e = getattr(o, fn)(a, [4], "max", dt)
+            assert np.array_equal(i, inc_max) and np.array_equal(e, exc_max), (fn, dt, i, e)
+    pts = np.arange(8)
+    assert np.array_equal(o.point_inc(a, [4], "sum", "i64", pts), inc_sum)
+    assert np.array_equal(o.point_exc(a, [4], "sum", "i64", pts), exc_sum)
+    assert np.array_equal(o.point_exc_direct(a, [4], "sum", "i64", pts), exc_sum)
+    assert np.array_equal(o.point_exc(a, [4], "max", "i64", pts), exc_max)
+
+
+def pin_hand_2d(o):
+    # 3 x 4 matrix 1..12, box (2, 2); boxes clip at the high edges.
+    a = np.arange(1, 13).reshape(3, 4)
+    inc_sum = np.array([[1 + 2 + 5 + 6, 2 + 3 + 6 + 7, 3 + 4 + 7 + 8, 4 + 8],
+                        [5 + 6 + 9 + 10, 6 + 7 + 10 + 11, 7 + 8 + 11 + 12, 8 + 12],
+                        [9 + 10, 10 + 11, 11 + 12, 12]])
+    exc_sum = 78 - inc_sum  # 78 = 1 + ... + 12, and the box partitions the rest
+    inc_max = np.array([[6, 7, 8, 8], [10, 11, 12, 12], [10, 11, 12, 12]])
+    # 12 sits at (2, 3): only the boxes at (1,2), (1,3), (2,2), (2,3) hold it
+    exc_max = np.array([[12, 12, 12, 12], [12, 12, 10, 11], [12, 12, 10, 11]])
+    for dt in ("i64", "f64"):
+        for fn in ("brute", "scale"):
+            i, e = getattr(o, fn)(a, [2, 2], "sum", dt)
+            assert np.array_equal(i, inc_sum) and np.array_equal(e, exc_sum), (fn, dt)
+            i, e = getattr(o, fn)(a, [2, 2], "max", dt)
+            assert np.array_equal(i, inc_max) and np.array_equal(e, exc_max), (fn, dt)
+        assert np.array_equal(o.corners2d(a, [2, 2], "sum", dt), exc_sum)
+        assert np.array_equal(o.corners2d(a, [2, 2], "max", dt), exc_max)
+
+
+# --------------------------------------------------------------------------
+# closed forms
+# --------------------------------------------------------------------------
+
+CLOSED_SHAPES = [((7,), (3,)), ((5, 6), (2, 4)), ((4, 3, 5), (3, 1, 2)),
+                 ((3, 4, 2, 3), (2, 4, 2, 1)), ((6, 5), (6, 5)), ((2, 3, 2, 2, 3), (1, 2, 2, 1, 3))]
+
+
+def pin_closed_forms(o):
+    for shape, k in CLOSED_SHAPES:
+        n = np.array(shape)
+        N = int(n.prod())
+        grids = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+        expect_inc = np.ones(shape, np.int64)
+        for ax in range(len(shape)):
+            expect_inc *= np.minimum(k[ax], shape[ax] - grids[ax])
+        ones = np.ones(shape, np.int64)
+        for fn in ("brute", "scale"):
+            i, e = getattr(o, fn)(ones, k, "sum", "i64")
+            assert np.array_equal(i, expect_inc), (fn, shape, k)
+            assert np.array_equal(e, N - expect_inc), (fn, shape, k)
+        # one-hot at p: included sum is 1 iff p lies in box(x)
+        rng = np.random.default_rng(len(shape))
+        p = tuple(int(rng.integers(0, s)) for s in shape)
+        hot = np.zeros(shape, np.int64)
+        hot[p] = 1
+        in_box = np.ones(shape, bool)
+        for ax in range(len(shape)):
+            in_box &= (grids[ax] <= p[ax]) & (p[ax] < grids[ax] + k[ax])
+        for fn in ("brute", "scale"):
+            i, e = getattr(o, fn)(hot, k, "sum", "i64")
+            assert np.array_equal(i, in_box.astype(np.int64)), (fn, shape, k, p)
+            assert np.array_equal(e, 1 - in_box.astype(np.int64)), (fn, shape, k, p)
+            # with max over {0, 1}, the same indicator
+            i, e = getattr(o, fn)(hot, k, "max", "i64")
+            if N > 1:
+                assert np.array_equal(i, in_box.astype(np.int64)), (fn, "max", shape, k, p)
+
+
+# --------------------------------------------------------------------------
+# textbook routines, written independently in numpy
+# --------------------------------------------------------------------------
+
+def sat_included_sum(a, k):
+    """Summed-area table (Crow): d-dim prefix sums plus inclusion-exclusion over
+    the 2^d corners of each box.  Integers only (exact)."""
+    a = np.asarray(a, dtype=np.int64)
+    d = a.ndim
+    S = np.zeros(tuple(s + 1 for s in a.shape), np.int64)
+    S[tuple(slice(1, None) for _ in range(d))] = a
+    for ax in range(d):
+        S = np.cumsum(S, axis=ax)
+    grids = np.meshgrid(*[np.arange(s) for s in a.shape], indexing="ij")
+    out = np.zeros(a.shape, np.int64)
+    for corner in itertools.product((0, 1), repeat=d):
+        idx = []
+        for ax in range(d):
+            hi = np.minimum(grids[ax] + k[ax], a.shape[ax])
+            idx.append(hi if corner[ax] else grids[ax])
+        sign = (-1) ** (d - sum(corner))
+        out += sign * S[tuple(idx)]
+    return out
+
+
+def window_max_included(a, k, ident):
+    """Sliding-window maximum over an identity-padded array."""
+    a = np.asarray(a)
+    pad = [(0, kk - 1) for kk in k]
+    p = np.pad(a, pad, constant_values=ident)
+    w = sliding_window_view(p, tuple(k))
+    return w.max(axis=tuple(range(a.ndim, 2 * a.ndim)))
+
+
+def masked_excluded(a, k, op, ident):
+    """For each cell, reduce A over a boolean mask of the complement of its box."""
+    a = np.asarray(a)
+    grids = np.meshgrid(*[np.arange(s) for s in a.shape], indexing="ij")
+    out = np.empty(a.shape, dtype=a.dtype if op == "max" else np.int64)
+    for x in itertools.product(*[range(s) for s in a.shape]):
+        inside = np.ones(a.shape, bool)
+        for ax in range(a.ndim):
+            inside &= (grids[ax] >= x[ax]) & (grids[ax] < x[ax] + k[ax])
+        vals = a[~inside]
+        if op == "sum":
+            out[x] = vals.astype(np.int64).sum()
+        else:
+            out[x] = vals.max() if vals.size else ident
+    return out
+
+
+TEXTBOOK_CASES = [((9,), (4,)), ((8, 5), (3, 2)), ((5, 4, 6), (2, 3, 4)),
+                  ((4, 3, 3, 5), (3, 2, 1, 2)), ((10,), (10,)), ((3, 7), (3, 1))]
+
+
+def pin_textbook(o):
+    rng = np.random.default_rng(7)
+    for shape, k in TEXTBOOK_CASES:
+        a = rng.integers(-50, 51, size=shape).astype(np.int64)
+        sat = sat_included_sum(a, k)
+        tot = int(a.sum())
+        for fn in ("brute", "scale"):
+            i, e = getattr(o, fn)(a, k, "sum", "i64")
+            assert np.array_equal(i, sat), (fn, shape, k)
+            assert np.array_equal(e, tot - sat), (fn, shape, k)
+        wm = window_max_included(a, k, I64_MIN)
+        me = masked_excluded(a, k, "max", I64_MIN)
+        for fn in ("brute", "scale"):
+            i, e = getattr(o, fn)(a, k, "max", "i64")
+            assert np.array_equal(i, wm), (fn, "max", shape, k)
+            assert np.array_equal(e, me), (fn, "max", shape, k)
+        # floats: the window max is exact; the masked + is exact on integers
+        af = a.astype(np.float64) / 4.0
+        i, e = o.brute(af, k, "max", "f64")
+        assert np.array_equal(i, window_max_included(af, k, -np.inf))
+        assert np.array_equal(e, masked_excluded(af, k, "max", -np.inf))
+        i, e = o.scale(af, k, "sum", "f64")
+        assert np.array_equal(i, sat / 4.0) and np.array_equal(e, (tot - sat) / 4.0)
+
+
+def pin_i32_wrap(o):
+    # sums that overflow int32 wrap modulo 2^32 (numpy int32 arithmetic wraps)
+    a = np.full((4, 5), 2_000_000_000, dtype=np.int64)
+    a[1, 2] = -2_147_483_648
+    k = (2, 3)
+    sat64 = sat_included_sum(a, k)
+    expect_inc = sat64.astype(np.int32).astype(np.int64)  # mod 2^32
+    expect_exc = (int(a.sum()) - sat64).astype(np.int32).astype(np.int64)
+    for fn in ("brute", "scale"):
+        i, e = getattr(o, fn)(a, k, "sum", "i32")
+        assert np.array_equal(i, expect_inc), fn
+        assert np.array_equal(e, expect_exc), fn
+    pts = np.arange(20)
+    assert np.array_equal(o.point_inc(a, k, "sum", "i32", pts), expect_inc.reshape(-1))
+    assert np.array_equal(o.point_exc(a, k, "sum", "i32", pts), expect_exc.reshape(-1))
+
+
+# --------------------------------------------------------------------------
+# invariants
+# --------------------------------------------------------------------------
+
+def pin_invariants(o):
+    rng = np.random.default_rng(11)
+    for shape, k in [((6, 7), (3, 2)), ((4, 5, 3), (2, 5, 2)), ((3, 3, 3, 3), (2, 1, 3, 2))]:
+        a = rng.integers(-1000, 1001, size=shape).astype(np.int64)
+        i, e = o.brute(a, k, "sum", "i64")
+        assert np.all(i + e == a.sum())
+        i, e = o.brute(a, k, "max", "i64")
+        assert np.all(np.maximum(i, e) == a.max())
+        # permuting axes permutes the outputs
+        perm = tuple(reversed(range(len(shape))))
+        kp = tuple(k[p] for p in perm)
+        ip, ep = o.brute(np.transpose(a, perm).copy(), kp, "sum", "i64")
+        i, e = o.brute(a, k, "sum", "i64")
+        assert np.array_equal(ip, np.transpose(i, perm)) and np.array_equal(ep, np.transpose(e, perm))
+    # 1-D: excluded sum = prefix up to x-1 op suffix from x+k
+    for n, kk in [(11, 3), (12, 4), (5, 5), (9, 1)]:
+        a = rng.integers(-9, 10, size=n).astype(np.int64)
+        pre = np.concatenate([[0], np.cumsum(a)])                 # pre[t] = sum a[:t]
+        suf = np.concatenate([np.cumsum(a[::-1])[::-1], [0]])    # suf[t] = sum a[t:]
+        x = np.arange(n)
+        expect = pre[x] + suf[np.minimum(x + kk, n)]
+        for fn in ("brute", "scale"):
+            _, e = getattr(o, fn)(a, [kk], "sum", "i64")
+            assert np.array_equal(e, expect), (fn, n, kk)
+        premax = np.concatenate([[I64_MIN], np.maximum.accumulate(a)])
+        sufmax = np.concatenate([np.maximum.accumulate(a[::-1])[::-1], [I64_MIN]])
+        expect = np.maximum(premax[x], sufmax[np.minimum(x + kk, n)])
+        for fn in ("brute", "scale"):
+            _, e = getattr(o, fn)(a, [kk], "max", "i64")
+            assert np.array_equal(e, expect), (fn, "max", n, kk)
+    # k = n: the box at the origin covers the tensor, so its complement is empty
+    for dt, ident in (("i32", I32_MIN), ("i64", I64_MIN), ("f64", -np.inf)):
+        a = rng.integers(-5, 6, size=(3, 4)).astype(np.float64 if dt == "f64" else np.int64)
+        for fn in ("brute", "scale"):
+            _, e = getattr(o, fn)(a, [3, 4], "max", dt)
+            assert e[0, 0] == ident, (fn, dt, e[0, 0])
+            _, e = getattr(o, fn)(a, [3, 4], "sum", dt)
+            assert e[0, 0] == 0, (fn, dt)
+
+
+ALL_PINS = [pin_hand_1d, pin_hand_2d, pin_closed_forms, pin_textbook, pin_i32_wrap, pin_invariants]
+
+
+def run_all(o):
+    for pin in ALL_PINS:
+        pin(o)
