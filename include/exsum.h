@@ -1,0 +1,191 @@
+/*
+ * exsum.h -- C ABI of libexsum: multidimensional included and excluded sums
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Paper: H. Xu, S. Fraser, C. E. Leiserson, "Multidimensional Included and
+ * Excluded Sums", SIAM ACDA 2021 (arXiv 2106.00124).
+ *
+ * Problem (Sec. 2, Definition "Included and Excluded Sums"): given a
+ * d-dimensional tensor A over a monoid (S, op, e) and a box size k, produce
+ * for every coordinate x
+ *     included sum  Inc(x) = op over A[x_0 : x_0+k_0, ..., x_{d-1} : x_{d-1}+k_{d-1}]
+ *     excluded sum  Exc(x) = op over every element of A outside that box
+ * (coordinates past the end of the tensor contribute e; Sec. 1 and the colon
+ * notation of Sec. 2).  Both are the "strong" problems: no inverse of op is
+ * used, so max works as well as +.  Included sums follow the bidirectional
+ * box-sum (BDBS) algorithm (Sec. 3); excluded sums follow the box-complement
+ * algorithm (Secs. 4-5: Theorem "Recursive Box-complement", Corollary
+ * "Excluded-sum Components").
+ *
+ * Conventions shared by every call:
+ *   - Coordinates are 0-based.  Tensors are dense and row-major (C order):
+ *     dims[0] is the paper's dimension 1 (largest stride) and dims[d-1] is
+ *     contiguous.  Outputs have the input's shape and element type (Sec. 2:
+ *     the output is a tensor over the same monoid).
+ *   - Element types and operators: + on f32, f64, i32, i64 (integer + wraps
+ *     modulo 2^32 / 2^64, so it is associative and commutative); max on all
+ *     four.  Identity e: 0 for +, -inf for float max, the type's minimum for
+ *     integer max (the value of an excluded sum whose complement is empty).
+ *   - Preconditions: 1 <= d <= EXS_MAX_RANK; dims[i] >= 1; 1 <= box[i] <= dims[i]
+ *     (Sec. 1 requires k_i <= n_i); the product of dims fits in int64.
+ *   - Pointers named *_dev are device pointers (hipMalloc / PyTorch CUDA
+ *     tensors); the caller owns every buffer.  The library never allocates or
+ *     frees caller memory; plain calls take their scratch as a workspace
+ *     argument.
+ *   - Streams are passed as void* and must be a hipStream_t (NULL = the null
+ *     stream).  Calls enqueue work and return without synchronising; results
+ *     are valid once the stream has completed.
+ *   - Every call returns an exs_status; nothing throws or exits across the
+ *     ABI.  exs_last_error() returns a thread-local message for the last
+ *     failing call on the calling thread.
+ */
+#ifndef EXSUM_H
+#define EXSUM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EXS_MAX_RANK 8
+
+typedef enum {
+    EXS_OK = 0,
+    EXS_EINVAL = 1,        /* bad argument (shape, box, null pointer, aliasing) */
+    EXS_EUNSUPPORTED = 2,  /* valid request this build does not implement */
+    EXS_ENOMEM = 3,        /* workspace too small, or a host allocation failed */
+    EXS_EDEVICE = 4,       /* a HIP call failed (message in exs_last_error) */
+    EXS_EAGAIN = 5,        /* resource temporarily unavailable */
+    EXS_ENOTREADY = 6,     /* asynchronous result not complete yet */
+    EXS_ENOTFOUND = 7      /* unknown ticket / handle */
+} exs_status;
+
+typedef enum { EXS_F32 = 0, EXS_F64 = 1, EXS_I32 = 2, EXS_I64 = 3 } exs_dtype;
+typedef enum { EXS_SUM = 0, EXS_MAX = 1 } exs_op;
+
+/* mode bit-mask */
+#define EXS_INCLUDED 1u
+#define EXS_EXCLUDED 2u
+
+/* One included/excluded-sums problem on one tensor.
+ *   d            rank, 1..EXS_MAX_RANK
+ *   dtype, op    element type and operator (see above)
+ *   mode         EXS_INCLUDED, EXS_EXCLUDED or both
+ *   dims[0..d)   tensor side lengths n_i
+ *   box[0..d)    box side lengths k_i
+ *   in_dev       input tensor, prod(dims) elements
+ *   inc_out_dev  included sums (same shape), required iff mode has EXS_INCLUDED
+ *   exc_out_dev  excluded sums (same shape), required iff mode has EXS_EXCLUDED
+ * Outputs must not overlap the input or each other. */
+typedef struct exs_job {
+    int32_t d;
+    int32_t dtype;
+    int32_t op;
+    uint32_t mode;
+    int64_t dims[EXS_MAX_RANK];
+    int64_t box[EXS_MAX_RANK];
+    const void *in_dev;
+    void *inc_out_dev;
+    void *exc_out_dev;
+} exs_job;
+
+/* ---------------------------------------------------------------------- */
+/* Plain single-tensor call                                                 */
+/* ---------------------------------------------------------------------- */
+
+/* Bytes of device workspace exs_run needs for this job (0 is possible).
+ * Validates the job's shape/box/dtype/op/mode; pointers are not inspected. */
+exs_status exs_workspace_size(const exs_job *job, size_t *bytes);
+
+/* Included and/or excluded sums of job->in_dev (Secs. 3-5).  ws_dev must be
+ * at least exs_workspace_size() bytes of device memory, 256-byte aligned,
+ * owned by the caller and not used by other work until the stream reaches
+ * this call's end.  Enqueued on `stream`; no host synchronisation. */
+exs_status exs_run(const exs_job *job, void *ws_dev, size_t ws_bytes, void *stream);
+
+/* Human-readable name of a status, and the calling thread's last error. */
+const char *exs_status_str(exs_status s);
+const char *exs_last_error(void);
+
+/* Library version string and the device architecture it was built for. */
+const char *exs_version(void);
+
+/* ---------------------------------------------------------------------- */
+/* Input generation on the device (workload support, not part of the method) */
+/* ---------------------------------------------------------------------- */
+
+/* Fill `count` elements at out_dev with the counter-based generator: element
+ * i is derived from output i of a SplitMix64 stream started at `seed`
+ * (Steele, Lea, Flood 2014).  kind 0: f32 "normalish" (sum of four 16-bit
+ * uniforms, centred and scaled to unit variance); kind 1: uniform integer in
+ * [lo, hi] for EXS_I32 / EXS_I64; kind 2: f32 with random sign and magnitude
+ * 2^e * (1 + m/2^23), e uniform in [-10, 9].  Bit-identical to the host twin
+ * in paper_2106_00124_amd/workloads.py. */
+exs_status exs_fill(void *out_dev, int64_t count, int32_t dtype, int32_t kind,
+                    uint64_t seed, int64_t lo, int64_t hi, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Batched form: many tensors of uneven shapes, ranks, boxes, dtypes and    */
+/* operators computed by one hipGraph launch of persistent work-list kernels */
+/* ---------------------------------------------------------------------- */
+
+typedef struct exs_batch exs_batch;
+
+/* Plan a batch of n jobs (copied; the job pointers are bound at create time
+ * and must stay valid for every launch).  tune_cache: path of the JSON
+ * autotune cache to read and update, or NULL for built-in tile choices.
+ * The call may time candidate tile shapes on the device (autotuning), which
+ * synchronises the device and writes the outputs of the jobs. */
+exs_status exs_batch_create(const exs_job *jobs, int32_t n, const char *tune_cache,
+                            exs_batch **out);
+/* Device workspace the batch needs. */
+exs_status exs_batch_workspace_size(const exs_batch *b, size_t *bytes);
+/* Enqueue the whole batch on `stream` as one graph launch (the graph is
+ * captured on the first call for this workspace and replayed afterwards). */
+exs_status exs_batch_launch(exs_batch *b, void *ws_dev, size_t ws_bytes, void *stream);
+/* The same work as individual kernel launches (no graph), for comparison. */
+exs_status exs_batch_launch_eager(exs_batch *b, void *ws_dev, size_t ws_bytes, void *stream);
+/* Number of kernel nodes in the captured graph and work items in the lists. */
+exs_status exs_batch_info(const exs_batch *b, int32_t *graph_nodes, int64_t *work_items);
+void exs_batch_destroy(exs_batch *b);
+
+/* ---------------------------------------------------------------------- */
+/* Serving form: continuous batching of excluded-sum requests               */
+/* ---------------------------------------------------------------------- */
+
+typedef struct exs_server exs_server;
+
+/* A server owns a device arena of hbm_budget bytes (allocated here, freed by
+ * destroy) from which it carves each request's output and workspace, and up
+ * to max_inflight HIP streams.  A dispatcher thread admits requests in
+ * arrival order while their bytes fit the free budget and a stream slot is
+ * free; admitted work overlaps on the device. */
+exs_status exs_server_create(size_t hbm_budget, int32_t max_inflight, exs_server **out);
+/* Queue a request.  job->in_dev must stay valid until the ticket completes;
+ * job->mode selects outputs; output pointers in the job are ignored (the
+ * server allocates them).  Never blocks; fails only for an invalid job or one
+ * larger than the whole budget (EXS_ENOMEM). */
+exs_status exs_server_submit(exs_server *s, const exs_job *job, uint64_t *ticket);
+/* EXS_OK and the device pointers of the outputs once the request completed,
+ * EXS_ENOTREADY before.  Pointers stay valid until release. */
+exs_status exs_server_poll(exs_server *s, uint64_t ticket, const void **inc_dev,
+                           const void **exc_dev, double *latency_ms);
+/* Block until every submitted request has completed. */
+exs_status exs_server_drain(exs_server *s);
+/* Return a completed request's memory to the arena. */
+exs_status exs_server_release(exs_server *s, uint64_t ticket);
+/* Latency percentiles (submit -> completion event) and throughput over the
+ * completed requests so far; queue depth and peak in-flight bytes. */
+exs_status exs_server_stats(exs_server *s, double *p50_ms, double *p99_ms,
+                            double *req_per_s, double *gelem_per_s,
+                            int64_t *completed, int64_t *max_queue,
+                            int64_t *peak_bytes);
+void exs_server_destroy(exs_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EXSUM_H */

@@ -1,1 +1,110 @@
-"""MI355X-native multidimensional included and excluded sums (HIP for gfx950)."""
+"""MI355X-native multidimensional included and excluded sums (HIP for gfx950).
+
+Paper: Xu, Fraser, Leiserson, "Multidimensional Included and Excluded Sums"
+(SIAM ACDA 2021, arXiv 2106.00124).
+
+Python binding of ``libexsum.so`` (C ABI in ``include/exsum.h``).  PyTorch is
+used only for device memory and streams; every step of the computation runs
+in the library's HIP kernels.  Nothing here computes on the host.
+
+    inc, exc = run(x, box, op="sum", mode="both")
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import ExsError  # noqa: F401
+
+_DTYPES = None
+
+
+def _dtype_code(t):
+    import torch
+    global _DTYPES
+    if _DTYPES is None:
+        _DTYPES = {torch.float32: _lib.F32, torch.float64: _lib.F64,
+                   torch.int32: _lib.I32, torch.int64: _lib.I64}
+    try:
+        return _DTYPES[t]
+    except KeyError:
+        raise ExsError(1, f"unsupported dtype {t}") from None
+
+
+_OPS = {"sum": _lib.SUM, "+": _lib.SUM, "max": _lib.MAX}
+_MODES = {"inc": _lib.INCLUDED, "included": _lib.INCLUDED, "exc": _lib.EXCLUDED,
+          "excluded": _lib.EXCLUDED, "both": _lib.INCLUDED | _lib.EXCLUDED}
+
+
+def _mode_code(mode):
+    if isinstance(mode, int):
+        return mode
+    return _MODES[mode]
+
+
+def job_for(x, box, op="sum", mode="both", inc_out=None, exc_out=None):
+    """Build an ``exs_job`` for device tensor ``x`` (outputs may be None)."""
+    box = [int(v) for v in box]
+    return _lib.make_job(x.dim(), _dtype_code(x.dtype), _OPS[op], _mode_code(mode),
+                         list(x.shape), box, x.data_ptr(),
+                         inc_out.data_ptr() if inc_out is not None else None,
+                         exc_out.data_ptr() if exc_out is not None else None)
+
+
+def workspace_size(shape, box, dtype, op="sum", mode="both") -> int:
+    """Workspace bytes ``run`` needs (dtype: a torch dtype)."""
+    j = _lib.make_job(len(shape), _dtype_code(dtype), _OPS[op], _mode_code(mode),
+                      list(shape), list(box), None, None, None)
+    n = ctypes.c_size_t()
+    _lib.check(_lib.lib().exs_workspace_size(ctypes.byref(j), ctypes.byref(n)))
+    return n.value
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def run(x, box, op="sum", mode="both", inc_out=None, exc_out=None, workspace=None,
+        stream=None):
+    """Included and/or excluded sums of the contiguous device tensor ``x``.
+
+    Returns ``(inc, exc)`` (None for an output not requested).  The work is
+    enqueued on ``stream`` (default: torch's current stream) without a host
+    synchronisation.  ``workspace`` may be a preallocated uint8 device tensor.
+    """
+    import torch
+    if not x.is_cuda:
+        raise ExsError(1, "x must be a device tensor")
+    if not x.is_contiguous():
+        raise ExsError(1, "x must be contiguous")
+    m = _mode_code(mode)
+    if m & _lib.INCLUDED and inc_out is None:
+        inc_out = torch.empty_like(x)
+    if m & _lib.EXCLUDED and exc_out is None:
+        exc_out = torch.empty_like(x)
+    j = job_for(x, box, op, m, inc_out if m & _lib.INCLUDED else None,
+                exc_out if m & _lib.EXCLUDED else None)
+    n = ctypes.c_size_t()
+    _lib.check(_lib.lib().exs_workspace_size(ctypes.byref(j), ctypes.byref(n)))
+    if workspace is None or workspace.numel() < n.value:
+        workspace = torch.empty(max(n.value, 1), dtype=torch.uint8, device=x.device)
+    _lib.check(_lib.lib().exs_run(ctypes.byref(j), ctypes.c_void_p(workspace.data_ptr()),
+                                  workspace.numel(), _stream_ptr(stream)))
+    return (inc_out if m & _lib.INCLUDED else None, exc_out if m & _lib.EXCLUDED else None)
+
+
+FILL_NORMALISH, FILL_UNIFORM_INT, FILL_LOGMAG = 0, 1, 2
+
+
+def fill(out, kind, seed, lo=-100, hi=100, stream=None):
+    """Fill device tensor ``out`` with the counter-based generator (see exsum.h)."""
+    _lib.check(_lib.lib().exs_fill(ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                   _dtype_code(out.dtype), kind, ctypes.c_uint64(seed),
+                                   lo, hi, _stream_ptr(stream)))
+    return out
+
+
+def version() -> str:
+    return _lib.lib().exs_version().decode()

@@ -1,0 +1,156 @@
+// exsum_device.hpp -- device building blocks for included and excluded sums
+// on gfx950 (CDNA4, wave64).
+//
+// Paper: Xu, Fraser, Leiserson, "Multidimensional Included and Excluded Sums"
+// (SIAM ACDA 2021, arXiv 2106.00124).
+//
+// Every routine here works on a tensor viewed as (outer, n, inner): `n` is the
+// length of the axis being processed and `inner` its stride.  Elements past
+// the end of an axis behave as the monoid identity (Sec. 1: out-of-range
+// coordinates contribute e; the footnote of Sec. 3 allows identity padding
+// when n is not a multiple of k).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef long long i64;
+
+namespace exs {
+
+// ---------------------------------------------------------------------------
+// The monoids: + (integer + wraps, done in unsigned arithmetic) and max.
+// Both are commutative, which the dimension-reduction reordering relies on.
+// ---------------------------------------------------------------------------
+struct OpSum {
+    template <typename T> static __device__ __forceinline__ T id() { return T(0); }
+    static __device__ __forceinline__ float apply(float a, float b) { return a + b; }
+    static __device__ __forceinline__ double apply(double a, double b) { return a + b; }
+    static __device__ __forceinline__ int apply(int a, int b) {
+        return (int)((unsigned)a + (unsigned)b);
+    }
+    static __device__ __forceinline__ long long apply(long long a, long long b) {
+        return (long long)((unsigned long long)a + (unsigned long long)b);
+    }
+};
+
+struct OpMax {
+    template <typename T> static __device__ __forceinline__ T id();
+    static __device__ __forceinline__ float apply(float a, float b) { return fmaxf(a, b); }
+    static __device__ __forceinline__ double apply(double a, double b) { return fmax(a, b); }
+    static __device__ __forceinline__ int apply(int a, int b) { return a > b ? a : b; }
+    static __device__ __forceinline__ long long apply(long long a, long long b) {
+        return a > b ? a : b;
+    }
+};
+template <> __device__ __forceinline__ float OpMax::id<float>() { return -__builtin_inff(); }
+template <> __device__ __forceinline__ double OpMax::id<double>() { return -__builtin_inf(); }
+template <> __device__ __forceinline__ int OpMax::id<int>() { return (int)0x80000000; }
+template <> __device__ __forceinline__ long long OpMax::id<long long>() {
+    return (long long)0x8000000000000000ULL;
+}
+
+__device__ __forceinline__ i64 gtid() {
+    return (i64)blockIdx.x * (i64)blockDim.x + (i64)threadIdx.x;
+}
+
+// ---------------------------------------------------------------------------
+// BDBS along one axis for one row (Sec. 3, "Included Sums in 1D"; App. B,
+// Fig. "Pseudocode for the 1D included sum", Lemma "Correctness in 1D").
+//
+// Blocks of k consecutive elements (aligned to multiples of k).  For each
+// block b the range suffix rsuf_b[r] = op of the block from r to its end and
+// the range prefix rpre_{b+1}[r-1] = op of the next block from its start to
+// r-1 give the window at x = b*k + r:
+//     out[x] = rsuf_b[0]                      if r == 0 (the whole block)
+//     out[x] = rsuf_b[r] op rpre_{b+1}[r-1]   otherwise
+// (0-based form of the combine; the proof of the lemma uses x mod k = 1 in
+// 1-based terms).  Positions past n are the identity.  The row is streamed
+// block by block with the suffixes of the current block in registers, so each
+// input is read once and each output written once.  KB >= k is a
+// compile-time bound on the block length so the arrays live in VGPRs.
+// Blocks [b0, b1) of the row are produced.
+// ---------------------------------------------------------------------------
+template <typename T, class Op, int KB>
+__device__ __forceinline__ void bdbs_row(const T* __restrict__ src, T* __restrict__ dst,
+                                         i64 n, i64 stride, int k, i64 b0, i64 b1) {
+    const T e = Op::template id<T>();
+    T cur[KB], nxt[KB];
+#pragma unroll
+    for (int r = 0; r < KB; ++r) {
+        const i64 x = b0 * k + r;
+        cur[r] = (r < k && x < n) ? src[x * stride] : e;
+    }
+    {
+        T s = e;
+#pragma unroll
+        for (int r = KB - 1; r >= 0; --r) {
+            if (r < k) { s = Op::apply(cur[r], s); cur[r] = s; }
+        }
+    }
+    for (i64 b = b0; b < b1; ++b) {
+        const i64 base = (b + 1) * k;
+#pragma unroll
+        for (int r = 0; r < KB; ++r) {
+            const i64 x = base + r;
+            nxt[r] = (r < k && x < n) ? src[x * stride] : e;
+        }
+        T p = e;
+#pragma unroll
+        for (int r = 0; r < KB; ++r) {
+            if (r < k) {
+                const i64 x = b * k + r;
+                T v = cur[r];
+                if (r > 0) { p = Op::apply(p, nxt[r - 1]); v = Op::apply(v, p); }
+                if (x < n) dst[x * stride] = v;
+            }
+        }
+        T s = e;
+#pragma unroll
+        for (int r = KB - 1; r >= 0; --r) {
+            if (r < k) { s = Op::apply(nxt[r], s); cur[r] = s; }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Streaming along axis 0 for one point m of the remaining axes (the "first
+// dimension-reduction step" of the box-complement algorithm, Sec. 5, with the
+// prefix and suffix steps merged; see the design notes):
+//
+//   Exc[x0] = (op over t < x0 of W[t]) op (op over t >= x0+k0 of W[t]) op Trest
+//   Inc[x0] = op over t in [x0, x0+k0) of W[t]            (BDBS along axis 0)
+//
+// W is the input already box-summed over the other axes.  The axis is cut in
+// blocks of k0; PX[q] / SX[q] are the op of the block totals of W strictly
+// before / after block q (computed from block aggregates of the input, then
+// box-summed over the other axes).  For x0 = q*k0 + r:
+//   prefix part = PX[q] op rpre_q[r-1]           (running, in registers)
+//   suffix part = rsuf_{q+1}[r] op SX[q+1]       (needs block q+1: one-block lag)
+// The caller supplies the block values through `nxt` (one block at a time).
+// ---------------------------------------------------------------------------
+template <typename T, class Op, int K0B>
+struct Axis0State {
+    T pex[K0B];   // prefix part for each row of the current block (Exc)
+    T rs[K0B];    // range suffix of the current block (Inc)
+    T P;          // op of everything before the next block (incl. Trest)
+
+    // Absorb block values v[0..k0) as the new current block.
+    __device__ __forceinline__ void absorb(const T (&v)[K0B], int k0, bool do_ex, bool do_inc) {
+        const T e = Op::template id<T>();
+        if (do_ex) {
+#pragma unroll
+            for (int r = 0; r < K0B; ++r) {
+                if (r < k0) { pex[r] = P; P = Op::apply(P, v[r]); }
+            }
+        }
+        if (do_inc) {
+            T s = e;
+#pragma unroll
+            for (int r = K0B - 1; r >= 0; --r) {
+                if (r < k0) { s = Op::apply(v[r], s); rs[r] = s; }
+            }
+        }
+    }
+};
+
+}  // namespace exs

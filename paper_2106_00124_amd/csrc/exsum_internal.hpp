@@ -1,0 +1,35 @@
+// exsum_internal.hpp -- declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/exsum.h"
+
+typedef long long i64;
+
+namespace exs {
+
+struct OpSum;
+struct OpMax;
+
+// generic-path launchers (exsum_kernels.hip)
+template <typename T, class Op>
+void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st);
+template <typename T, class Op>
+void launch_blockagg(const T* X, T* Ga, i64 n0, i64 M, i64 k0, i64 Q, hipStream_t st);
+template <typename T, class Op>
+void launch_blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M,
+                      hipStream_t st);
+template <typename T, class Op>
+void launch_axis0(const T* W, const T* PX, const T* SX, const T* Trest, T* exc, T* inc, i64 n0,
+                  i64 M, i64 k0, i64 Q, hipStream_t st);
+void launch_fill(void* out, i64 count, int dtype, int kind, uint64_t seed, i64 lo, i64 hi,
+                 float scale, hipStream_t st);
+
+// error plumbing (exsum_api.cpp)
+exs_status set_error(exs_status s, const std::string& msg);
+size_t dtype_size(int dtype);
+exs_status validate_job(const exs_job* job, bool check_ptrs);
+
+}  // namespace exs

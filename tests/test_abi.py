@@ -1,0 +1,97 @@
+"""The C-ABI library loads, exports every declared symbol, and validates jobs
+on the host (no GPU needed: no call here launches work)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "exsum.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(exs_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("exs_workspace_size", "exs_run", "exs_status_str", "exs_last_error",
+                 "exs_batch_create", "exs_batch_launch", "exs_server_create",
+                 "exs_server_submit", "exs_server_poll", "exs_server_stats"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2106_00124_amd import _lib
+    h = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(h, n)]
+    assert not missing, missing
+    assert set(declared_functions()) == set(_lib.SIGNATURES), \
+        set(declared_functions()) ^ set(_lib.SIGNATURES)
+
+
+def test_status_strings():
+    from paper_2106_00124_amd import _lib
+    L = _lib.lib()
+    for code, name in _lib.STATUS.items():
+        assert L.exs_status_str(code).decode() == name
+
+
+def _ws(shape, box, dtype=0, op=0, mode=3):
+    from paper_2106_00124_amd import _lib
+    j = _lib.make_job(len(shape), dtype, op, mode, shape, box, None, None, None)
+    n = ctypes.c_size_t()
+    st = _lib.lib().exs_workspace_size(ctypes.byref(j), ctypes.byref(n))
+    return st, n.value
+
+
+@pytest.mark.parametrize("shape,box,dtype,op,mode", [
+    ((4, 4), (0, 1), 0, 0, 3),       # k < 1
+    ((4, 4), (5, 1), 0, 0, 3),       # k > n
+    ((0, 4), (1, 1), 0, 0, 3),       # empty axis
+    ((4, 4), (1, 1), 9, 0, 3),       # bad dtype
+    ((4, 4), (1, 1), 0, 7, 3),       # bad op
+    ((4, 4), (1, 1), 0, 0, 0),       # no output
+    ((4, 4), (1, 1), 0, 0, 4),       # unknown mode bit
+])
+def test_invalid_jobs_rejected(shape, box, dtype, op, mode):
+    st, _ = _ws(shape, box, dtype, op, mode)
+    assert st == 1  # EXS_EINVAL
+
+
+def test_rank_limits():
+    from paper_2106_00124_amd import _lib
+    j = _lib.make_job(1, 0, 0, 3, [4], [2], None, None, None)
+    j.d = 9
+    n = ctypes.c_size_t()
+    assert _lib.lib().exs_workspace_size(ctypes.byref(j), ctypes.byref(n)) == 1
+    j.d = 0
+    assert _lib.lib().exs_workspace_size(ctypes.byref(j), ctypes.byref(n)) == 1
+
+
+def test_workspace_sizes_sane():
+    st, inc_only = _ws((512, 512, 512), (16, 16, 16), 0, 0, 1)
+    assert st == 0
+    st, both = _ws((512, 512, 512), (16, 16, 16), 0, 0, 3)
+    assert st == 0 and both >= inc_only
+    st, one_d = _ws((100,), (7,), 3, 1, 3)
+    assert st == 0 and one_d > 0
+    for d in range(1, 9):
+        st, n = _ws((3,) * d, (2,) * d, 2, 0, 3)
+        assert st == 0
+
+
+def test_run_rejects_null_and_aliasing_on_host():
+    """Argument checks happen before anything touches the device."""
+    from paper_2106_00124_amd import _lib
+    L = _lib.lib()
+    j = _lib.make_job(2, 0, 0, 3, [8, 8], [2, 2], 0x1000, None, 0x9000)
+    assert L.exs_run(ctypes.byref(j), None, 0, None) == 1          # inc_out NULL
+    j = _lib.make_job(2, 0, 0, 2, [8, 8], [2, 2], 0x1000, None, 0x1080)
+    assert L.exs_run(ctypes.byref(j), None, 0, None) == 1          # overlaps input
+    assert b"overlaps" in L.exs_last_error()
+    j = _lib.make_job(2, 0, 0, 2, [8, 8], [2, 2], 0x1000, None, 0x9000)
+    assert L.exs_run(ctypes.byref(j), None, 0, None) == 3          # workspace too small

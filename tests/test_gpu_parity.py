@@ -1,0 +1,71 @@
+"""HIP path vs the CPU oracle, element by element, on small seeded inputs.
+
+Shapes span several tiles/blocks and ragged tails (n mod k != 0), k = 1, k = n,
+boxes longer than 64 (the two-sweep kernels), ranks 1..8, every dtype x op.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_util import compare_full, gpu_run, make_input, say
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ((1,), (1,)),
+    ((37,), (5,)),
+    ((300,), (300,)),
+    ((1000,), (64,)),
+    ((777,), (100,)),            # k > 64: two-sweep kernels
+    ((64, 64), (8, 8)),
+    ((13, 70), (4, 9)),
+    ((70, 13), (13, 1)),
+    ((5, 300), (5, 65)),
+    ((9, 10, 11), (2, 3, 4)),
+    ((33, 17, 65), (16, 16, 16)),
+    ((4, 5, 6, 7), (4, 1, 3, 7)),
+    ((6, 5, 4, 3, 2), (3, 2, 4, 1, 2)),
+    ((3, 2, 3, 2, 3, 2), (2, 2, 1, 2, 3, 1)),
+    ((2, 2, 2, 2, 2, 2, 2, 3), (1, 2, 2, 1, 2, 2, 1, 2)),
+]
+
+DTYPE_OPS = [("f32", "sum"), ("f32", "max"), ("f64", "sum"), ("f64", "max"),
+             ("i32", "sum"), ("i32", "max"), ("i64", "sum"), ("i64", "max")]
+
+
+@pytest.mark.parametrize("shape,box", CASES, ids=lambda v: "x".join(map(str, v)))
+@pytest.mark.parametrize("dtype,op", DTYPE_OPS, ids=lambda v: str(v))
+def test_parity_small(orc, shape, box, dtype, op):
+    say(f"[parity] shape={shape} box={box} dtype={dtype} op={op}")
+    a = make_input(shape, dtype, seed=hash((shape, box, dtype, op)) % 2**32, op=op)
+    inc, exc = gpu_run(a, box, op, "both")
+    compare_full(orc, a, box, op, dtype, inc, exc, what=f"{shape} {box} {dtype} {op}")
+
+
+@pytest.mark.parametrize("mode", ["inc", "exc"])
+def test_single_output_modes(orc, mode):
+    shape, box = (20, 30, 40), (3, 5, 7)
+    a = make_input(shape, "i32", seed=5, op="sum")
+    inc, exc = gpu_run(a, box, "sum", mode)
+    assert (inc is None) == (mode == "exc") and (exc is None) == (mode == "inc")
+    compare_full(orc, a, box, "sum", "i32", inc, exc, what=mode)
+
+
+def test_config_d2_64x64_i64(orc):
+    """64x64 int64 in [-100, 100], box (8, 8), +: against brute force and corners."""
+    from paper_2106_00124_amd.workloads import WORKLOADS
+    w = WORKLOADS["d2_64x64_i64"]
+    a = w.tensor()
+    say(f"[config] {w.name}")
+    inc, exc = gpu_run(a, w.box, "sum", "both")
+    ri, re_ = orc.brute(a, w.box, "sum", "i64")
+    assert np.array_equal(inc, ri)
+    assert np.array_equal(exc, re_)
+    assert np.array_equal(exc, orc.corners2d(a, w.box, "sum", "i64"))
+    assert np.all(inc + exc == a.sum())
+
+
+def test_deterministic(orc):
+    a = make_input((40, 50, 60), "f32", seed=9, op="sum")
+    i1, e1 = gpu_run(a, (5, 6, 7), "sum")
+    i2, e2 = gpu_run(a, (5, 6, 7), "sum")
+    assert np.array_equal(i1, i2) and np.array_equal(e1, e2)
