@@ -112,6 +112,17 @@ const char *exs_last_error(void);
 /* Library version string and the device architecture it was built for. */
 const char *exs_version(void);
 
+/* Per-kernel timing (measurement support).  While enabled, every kernel the
+ * library enqueues is bracketed by a pair of HIP events recorded on the
+ * stream it is launched on.  exs_timing_read synchronises those events and
+ * returns, per kernel name, the number of launches and their summed duration
+ * in milliseconds (at most `max` entries, names NUL-terminated in 64-byte
+ * slots of `names`), then clears the record.  Host-side bookkeeping only;
+ * not thread-safe against concurrent exs_run calls. */
+exs_status exs_timing_enable(int32_t on);
+exs_status exs_timing_read(int32_t max, char *names, int64_t *launches, double *total_ms,
+                           int32_t *count);
+
 /* ---------------------------------------------------------------------- */
 /* Input generation on the device (workload support, not part of the method) */
 /* ---------------------------------------------------------------------- */

@@ -52,6 +52,11 @@ SIGNATURES = {
     "exs_version": (ctypes.c_char_p, []),
     "exs_fill": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                 ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, _P]),
+    "exs_timing_enable": (ctypes.c_int, [ctypes.c_int32]),
+    "exs_timing_read": (ctypes.c_int, [ctypes.c_int32, ctypes.c_char_p,
+                                       ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int32)]),
     "exs_batch_create": (ctypes.c_int, [_JP, ctypes.c_int32, ctypes.c_char_p,
                                         ctypes.POINTER(_P)]),
     "exs_batch_workspace_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),

@@ -22,7 +22,10 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "exsum_internal.hpp"
 
@@ -81,6 +84,50 @@ exs_status validate_job(const exs_job* job, bool check_ptrs) {
     return EXS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Per-kernel event timing
+// ---------------------------------------------------------------------------
+struct TimingRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+static std::mutex g_tmu;
+static bool g_timing = false;
+static std::vector<TimingRec> g_pending;
+static std::vector<hipEvent_t> g_event_pool;
+static thread_local int g_tag = -1;
+
+void set_timing_tag(int level) { g_tag = level; }
+
+static hipEvent_t take_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+KTimer::KTimer(const char* name, hipStream_t stream) : slot(-1), st(stream) {
+    std::lock_guard<std::mutex> g(g_tmu);
+    if (!g_timing) return;
+    std::string nm(name);
+    if (g_tag >= 0) nm += "@L" + std::to_string(g_tag);
+    TimingRec r{nm, take_event(), take_event()};
+    if (!r.a || !r.b) return;
+    hipEventRecord(r.a, st);
+    g_pending.push_back(r);
+    slot = (int)g_pending.size() - 1;
+}
+
+KTimer::~KTimer() {
+    if (slot < 0) return;
+    std::lock_guard<std::mutex> g(g_tmu);
+    if (slot < (int)g_pending.size()) hipEventRecord(g_pending[slot].b, st);
+}
+
 // Bump allocator over the caller's workspace.  In "dry" mode it only
 // measures, so sizing and execution share one code path.
 struct Arena {
@@ -136,6 +183,7 @@ static exs_status run_generic(const exs_job* job, Arena& ar, hipStream_t st) {
     T* wb0 = nwb >= 1 ? ar.take<T>(N) : nullptr;
     T* wb1 = nwb >= 2 ? ar.take<T>(N) : nullptr;
 
+    set_timing_tag(0);
     if (!(job->mode & EXS_EXCLUDED)) {
         // included sums only: BDBS along every axis
         const T* W = filter_axes<T, Op>(A, n, k, d, 1, wb0, wb1, dry, st);
@@ -172,6 +220,7 @@ static exs_status run_generic(const exs_job* job, Arena& ar, hipStream_t st) {
     for (int j = 0; j < d; ++j) {
         const int dj = d - j;
         const T* src = j == 0 ? A : R[j];
+        set_timing_tag(j);
         if (!dry) launch_blockagg<T, Op>(src, Ga, n[j], M[j], k[j], Q[j], st);
         i64 gn[EXS_MAX_RANK], gk[EXS_MAX_RANK];
         gn[0] = Q[j];
@@ -184,6 +233,7 @@ static exs_status run_generic(const exs_job* job, Arena& ar, hipStream_t st) {
     for (int j = d - 1; j >= 0; --j) {
         const int dj = d - j;
         const T* src = j == 0 ? A : R[j];
+        set_timing_tag(j);
         const T* W = filter_axes<T, Op>(src, n + j, k + j, dj, 1, wb0, wb1, dry, st);
         T* out = j == 0 ? exc : tb[j % 2];
         const T* Trest = j == d - 1 ? nullptr : tb[(j + 1) % 2];
@@ -245,6 +295,7 @@ exs_status exs_run(const exs_job* job, void* ws, size_t ws_bytes, void* stream) 
     ar.cap = ws_bytes;
     hipStream_t st = (hipStream_t)stream;
     s = dispatch(job, ar, st);
+    set_timing_tag(-1);
     if (s != EXS_OK) return s;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -269,6 +320,44 @@ const char* exs_status_str(exs_status s) {
 const char* exs_last_error(void) { return g_last_error.c_str(); }
 
 const char* exs_version(void) { return "exsum 0.1 (gfx950)"; }
+
+exs_status exs_timing_enable(int32_t on) {
+    std::lock_guard<std::mutex> g(g_tmu);
+    g_timing = on != 0;
+    return EXS_OK;
+}
+
+exs_status exs_timing_read(int32_t max, char* names, int64_t* launches, double* total_ms,
+                           int32_t* count) {
+    std::lock_guard<std::mutex> g(g_tmu);
+    std::map<std::string, std::pair<int64_t, double>> acc;
+    std::vector<std::string> order;
+    for (auto& r : g_pending) {
+        if (hipEventSynchronize(r.b) != hipSuccess)
+            return set_error(EXS_EDEVICE, "hipEventSynchronize failed");
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, r.a, r.b);
+        if (!acc.count(r.name)) order.push_back(r.name);
+        acc[r.name].first += 1;
+        acc[r.name].second += ms;
+        g_event_pool.push_back(r.a);
+        g_event_pool.push_back(r.b);
+    }
+    g_pending.clear();
+    int32_t c = 0;
+    for (auto& nm : order) {
+        if (c >= max) break;
+        if (names) {
+            std::strncpy(names + 64 * c, nm.c_str(), 63);
+            names[64 * c + 63] = 0;
+        }
+        if (launches) launches[c] = acc[nm].first;
+        if (total_ms) total_ms[c] = acc[nm].second;
+        ++c;
+    }
+    if (count) *count = c;
+    return EXS_OK;
+}
 
 exs_status exs_fill(void* out, int64_t count, int32_t dtype, int32_t kind, uint64_t seed,
                     int64_t lo, int64_t hi, void* stream) {

@@ -27,6 +27,16 @@ void launch_axis0(const T* W, const T* PX, const T* SX, const T* Trest, T* exc, 
 void launch_fill(void* out, i64 count, int dtype, int kind, uint64_t seed, i64 lo, i64 hi,
                  float scale, hipStream_t st);
 
+// per-kernel event timing (exsum_api.cpp); a no-op unless enabled.  The
+// planner tags launches with the recursion level they belong to.
+void set_timing_tag(int level);
+struct KTimer {
+    int slot;
+    hipStream_t st;
+    KTimer(const char* name, hipStream_t stream);
+    ~KTimer();
+};
+
 // error plumbing (exsum_api.cpp)
 exs_status set_error(exs_status s, const std::string& msg);
 size_t dtype_size(int dtype);

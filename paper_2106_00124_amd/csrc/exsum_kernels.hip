@@ -263,6 +263,7 @@ static inline int bucket_for(i64 k) {
 template <typename T, class Op>
 void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st) {
     const int kb = bucket_for(k);
+    KTimer timer(kb == 0 ? "k_bdbs_2sweep" : "k_bdbs", st);
     if (kb == 0) {
         hipLaunchKernelGGL((k_bdbs_2sweep<T, Op>), dim3(grid_for(O * I)), dim3(256), 0, st,
                            in, out, O, n, I, k);
@@ -290,6 +291,7 @@ void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st
 
 template <typename T, class Op>
 void launch_blockagg(const T* X, T* Ga, i64 n0, i64 M, i64 k0, i64 Q, hipStream_t st) {
+    KTimer timer("k_blockagg", st);
     hipLaunchKernelGGL((k_blockagg<T, Op>), dim3(grid_for(Q * M)), dim3(256), 0, st, X, Ga, n0,
                        M, k0, Q);
 }
@@ -297,6 +299,7 @@ void launch_blockagg(const T* X, T* Ga, i64 n0, i64 M, i64 k0, i64 Q, hipStream_
 template <typename T, class Op>
 void launch_blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M,
                       hipStream_t st) {
+    KTimer timer("k_blockscan", st);
     hipLaunchKernelGGL((k_blockscan<T, Op>), dim3(grid_for(M)), dim3(256), 0, st, Gw, Ga, PX,
                        SX, R, Q, M);
 }
@@ -306,6 +309,7 @@ void launch_axis0(const T* W, const T* PX, const T* SX, const T* Trest, T* exc, 
                   i64 M, i64 k0, i64 Q, hipStream_t st) {
     const int kb = bucket_for(k0);
     if (kb == 0) {
+        KTimer timer("k_ex1d_2sweep", st);
         if (exc)
             hipLaunchKernelGGL((k_ex1d_2sweep<T, Op>), dim3(grid_for(M)), dim3(256), 0, st, W,
                                Trest, exc, n0, M, k0);
@@ -318,6 +322,7 @@ void launch_axis0(const T* W, const T* PX, const T* SX, const T* Trest, T* exc, 
     const i64 segblocks = (Q + nseg - 1) / nseg;
     nseg = (Q + segblocks - 1) / segblocks;
     const unsigned g = grid_for(nseg * M);
+    KTimer timer("k_axis0", st);
 #define EXS_AX0_CASE(KB)                                                                    \
     case KB:                                                                                \
         hipLaunchKernelGGL((k_axis0<T, Op, KB>), dim3(g), dim3(256), 0, st, W, PX, SX, Trest, \
@@ -335,6 +340,7 @@ void launch_fill(void* out, i64 count, int dtype, int kind, uint64_t seed, i64 l
     i64 g = (count + 255) / 256;
     if (g > 65536) g = 65536;
     if (g < 1) g = 1;
+    KTimer timer("k_fill", st);
     hipLaunchKernelGGL(k_fill, dim3((unsigned)g), dim3(256), 0, st, out, count, dtype, kind,
                        seed, lo, hi, scale);
 }
