@@ -149,16 +149,16 @@ static i64 prod(const i64* v, int a, int b) {
     return p;
 }
 
-// Box-sum a rank-d tensor over axes d-1 .. first (last axis first: the
+// Box-sum a rank-d tensor over axes last .. first (last axis first: the
 // innermost reduction of the nested definition in Sec. 2), ping-ponging
 // between wb[0] and wb[1].  Returns the result (src itself if no axis).
 template <typename T, class Op>
-static const T* filter_axes(const T* src, const i64* n, const i64* k, int d, int first, T* wb0,
-                            T* wb1, bool dry, hipStream_t st) {
+static const T* filter_axes(const T* src, const i64* n, const i64* k, int d, int first, int last,
+                            T* wb0, T* wb1, bool dry, hipStream_t st) {
     const T* cur = src;
     T* wb[2] = {wb0, wb1};
     int which = 0;
-    for (int a = d - 1; a >= first; --a) {
+    for (int a = last; a >= first; --a) {
         T* dst = wb[which];
         which ^= 1;
         if (!dry) launch_bdbs<T, Op>(cur, dst, prod(n, 0, a), n[a], prod(n, a + 1, d), k[a], st);
@@ -175,18 +175,39 @@ static exs_status run_generic(const exs_job* job, Arena& ar, hipStream_t st) {
     const T* A = (const T*)job->in_dev;
     T* inc = (job->mode & EXS_INCLUDED) ? (T*)job->inc_out_dev : nullptr;
     T* exc = (job->mode & EXS_EXCLUDED) ? (T*)job->exc_out_dev : nullptr;
+    const bool want_exc = job->mode & EXS_EXCLUDED;
     const bool dry = ar.dry;
     const i64 N = prod(n, 0, d);
+    // level 0 streams axis 0 with the fused plane kernel when it applies; it
+    // box-sums the two trailing axes itself, the middle axes are done first
+    const bool fused = plane_eligible(d, n, k, (int)sizeof(T));
 
-    // buffers for the box-summed tensors (shared by every level)
-    const int nwb = std::min(2, d - 1);
-    T* wb0 = nwb >= 1 ? ar.take<T>(N) : nullptr;
-    T* wb1 = nwb >= 2 ? ar.take<T>(N) : nullptr;
+    // buffers for box-summed tensors, shared by every level: level j needs
+    // (d_j - 1) passes over N_j elements, the fused level 0 only d - 3
+    int wb_count = 0;
+    i64 wb_elems = 0;
+    for (int j = 0; j < (want_exc ? d : 1); ++j) {
+        const int passes = (j == 0 && fused) ? std::max(0, d - 3) : d - j - 1;
+        if (passes > 0) {
+            wb_count = std::max(wb_count, std::min(2, passes));
+            wb_elems = std::max(wb_elems, prod(n, j, d));
+        }
+    }
+    T* wb0 = wb_count >= 1 ? ar.take<T>(wb_elems) : nullptr;
+    T* wb1 = wb_count >= 2 ? ar.take<T>(wb_elems) : nullptr;
 
     set_timing_tag(0);
-    if (!(job->mode & EXS_EXCLUDED)) {
+    if (!want_exc) {
         // included sums only: BDBS along every axis
-        const T* W = filter_axes<T, Op>(A, n, k, d, 1, wb0, wb1, dry, st);
+        if (fused) {
+            const T* X0 = filter_axes<T, Op>(A, n, k, d, 1, d - 3, wb0, wb1, dry, st);
+            if (!dry)
+                launch_plane_axis0<T, Op>(X0, nullptr, nullptr, nullptr, nullptr, inc, n[0],
+                                          prod(n, 1, d - 2), n[d - 2], n[d - 1], k[0], k[d - 2],
+                                          k[d - 1], (n[0] + k[0] - 1) / k[0], st);
+            return EXS_OK;
+        }
+        const T* W = filter_axes<T, Op>(A, n, k, d, 1, d - 1, wb0, wb1, dry, st);
         if (!dry) launch_bdbs<T, Op>(W, inc, 1, n[0], prod(n, 1, d), k[0], st);
         return EXS_OK;
     }
@@ -226,7 +247,7 @@ static exs_status run_generic(const exs_job* job, Arena& ar, hipStream_t st) {
         gn[0] = Q[j];
         gk[0] = 1;
         for (int a = 1; a < dj; ++a) { gn[a] = n[j + a]; gk[a] = k[j + a]; }
-        const T* Gw = filter_axes<T, Op>(Ga, gn, gk, dj, 1, gb0, gb1, dry, st);
+        const T* Gw = filter_axes<T, Op>(Ga, gn, gk, dj, 1, dj - 1, gb0, gb1, dry, st);
         if (!dry) launch_blockscan<T, Op>(Gw, Ga, PX[j], SX[j], R[j + 1], Q[j], M[j], st);
     }
     // bottom-up: stream the first axis of each level, adding the level below
@@ -234,9 +255,17 @@ static exs_status run_generic(const exs_job* job, Arena& ar, hipStream_t st) {
         const int dj = d - j;
         const T* src = j == 0 ? A : R[j];
         set_timing_tag(j);
-        const T* W = filter_axes<T, Op>(src, n + j, k + j, dj, 1, wb0, wb1, dry, st);
         T* out = j == 0 ? exc : tb[j % 2];
         const T* Trest = j == d - 1 ? nullptr : tb[(j + 1) % 2];
+        if (j == 0 && fused) {
+            const T* X0 = filter_axes<T, Op>(A, n, k, d, 1, d - 3, wb0, wb1, dry, st);
+            if (!dry)
+                launch_plane_axis0<T, Op>(X0, PX[0], SX[0], Trest, exc, inc, n[0],
+                                          prod(n, 1, d - 2), n[d - 2], n[d - 1], k[0], k[d - 2],
+                                          k[d - 1], Q[0], st);
+            continue;
+        }
+        const T* W = filter_axes<T, Op>(src, n + j, k + j, dj, 1, dj - 1, wb0, wb1, dry, st);
         if (!dry)
             launch_axis0<T, Op>(W, PX[j], SX[j], Trest, out, j == 0 ? inc : nullptr, n[j], M[j],
                                 k[j], Q[j], st);

@@ -24,6 +24,11 @@ void launch_blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M
 template <typename T, class Op>
 void launch_axis0(const T* W, const T* PX, const T* SX, const T* Trest, T* exc, T* inc, i64 n0,
                   i64 M, i64 k0, i64 Q, hipStream_t st);
+template <typename T, class Op>
+void launch_plane_axis0(const T* X, const T* PX, const T* SX, const T* Trest, T* exc, T* inc,
+                        i64 n0, i64 MID, i64 NY, i64 NX, i64 k0, i64 ky, i64 kx, i64 Q,
+                        hipStream_t st);
+bool plane_eligible(int d, const i64* n, const i64* k, int es);
 void launch_fill(void* out, i64 count, int dtype, int kind, uint64_t seed, i64 lo, i64 hi,
                  float scale, hipStream_t st);
 

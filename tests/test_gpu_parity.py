@@ -41,6 +41,35 @@ def test_parity_small(orc, shape, box, dtype, op):
     compare_full(orc, a, box, op, dtype, inc, exc, what=f"{shape} {box} {dtype} {op}")
 
 
+# rank >= 3 cases that take the fused plane kernel: several tiles in both
+# plane axes, several runs of blocks along axis 0, each k0 bucket (which sets
+# the workgroup size and tile), boxes at the tile limit, middle axes (d >= 4)
+PLANE_CASES = [
+    ((40, 70, 90), (5, 7, 9)),
+    ((100, 33, 65), (16, 16, 16)),
+    ((70, 40, 50), (33, 5, 6)),
+    ((64, 20, 30), (20, 16, 16)),
+    ((130, 17, 19), (1, 1, 1)),
+    ((3, 100, 100), (3, 16, 16)),
+    ((7, 45, 70), (2, 32, 32)),
+    ((5, 6, 7, 40, 50), (2, 3, 4, 5, 6)),
+    ((16, 8, 64, 64), (8, 8, 4, 4)),
+]
+
+
+@pytest.mark.parametrize("shape,box", PLANE_CASES, ids=lambda v: "x".join(map(str, v)))
+@pytest.mark.parametrize("dtype,op", DTYPE_OPS, ids=lambda v: str(v))
+def test_parity_plane(orc, shape, box, dtype, op):
+    say(f"[plane] shape={shape} box={box} dtype={dtype} op={op}")
+    a = make_input(shape, dtype, seed=hash((shape, box, dtype, op, 1)) % 2**32, op=op)
+    inc, exc = gpu_run(a, box, op, "both")
+    compare_full(orc, a, box, op, dtype, inc, exc, what=f"{shape} {box} {dtype} {op}")
+    if dtype == "i32" and op == "sum":
+        for mode in ("inc", "exc"):
+            i2, e2 = gpu_run(a, box, op, mode)
+            assert np.array_equal(i2 if mode == "inc" else e2, inc if mode == "inc" else exc)
+
+
 @pytest.mark.parametrize("mode", ["inc", "exc"])
 def test_single_output_modes(orc, mode):
     shape, box = (20, 30, 40), (3, 5, 7)
