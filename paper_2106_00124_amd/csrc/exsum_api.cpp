@@ -167,6 +167,15 @@ static const T* filter_axes(const T* src, const i64* n, const i64* k, int d, int
     return cur;
 }
 
+// The fused plane kernel is built for 4-byte element types only.
+template <typename T, class Op>
+static void plane_call(const T* X, const T* PX, const T* SX, const T* Trest, T* exc, T* inc,
+                       i64 n0, i64 MID, i64 NY, i64 NX, i64 k0, i64 ky, i64 kx, i64 Q,
+                       hipStream_t st) {
+    if constexpr (sizeof(T) == 4)
+        launch_plane_axis0<T, Op>(X, PX, SX, Trest, exc, inc, n0, MID, NY, NX, k0, ky, kx, Q, st);
+}
+
 template <typename T, class Op>
 static exs_status run_generic(const exs_job* job, Arena& ar, hipStream_t st) {
     const int d = job->d;
@@ -180,7 +189,7 @@ static exs_status run_generic(const exs_job* job, Arena& ar, hipStream_t st) {
     const i64 N = prod(n, 0, d);
     // level 0 streams axis 0 with the fused plane kernel when it applies; it
     // box-sums the two trailing axes itself, the middle axes are done first
-    const bool fused = plane_eligible(d, n, k, (int)sizeof(T));
+    const bool fused = sizeof(T) == 4 && plane_eligible(d, n, k, (int)sizeof(T));
 
     // buffers for box-summed tensors, shared by every level: level j needs
     // (d_j - 1) passes over N_j elements, the fused level 0 only d - 3
@@ -202,7 +211,7 @@ static exs_status run_generic(const exs_job* job, Arena& ar, hipStream_t st) {
         if (fused) {
             const T* X0 = filter_axes<T, Op>(A, n, k, d, 1, d - 3, wb0, wb1, dry, st);
             if (!dry)
-                launch_plane_axis0<T, Op>(X0, nullptr, nullptr, nullptr, nullptr, inc, n[0],
+                plane_call<T, Op>(X0, nullptr, nullptr, nullptr, nullptr, inc, n[0],
                                           prod(n, 1, d - 2), n[d - 2], n[d - 1], k[0], k[d - 2],
                                           k[d - 1], (n[0] + k[0] - 1) / k[0], st);
             return EXS_OK;
@@ -260,7 +269,7 @@ static exs_status run_generic(const exs_job* job, Arena& ar, hipStream_t st) {
         if (j == 0 && fused) {
             const T* X0 = filter_axes<T, Op>(A, n, k, d, 1, d - 3, wb0, wb1, dry, st);
             if (!dry)
-                launch_plane_axis0<T, Op>(X0, PX[0], SX[0], Trest, exc, inc, n[0],
+                plane_call<T, Op>(X0, PX[0], SX[0], Trest, exc, inc, n[0],
                                           prod(n, 1, d - 2), n[d - 2], n[d - 1], k[0], k[d - 2],
                                           k[d - 1], Q[0], st);
             continue;

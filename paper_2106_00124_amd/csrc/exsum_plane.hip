@@ -38,32 +38,66 @@ struct PlaneArgs {
     i64 tilesY, tilesX, segblocks, nseg;
 };
 
-template <int K0B, int ES>
+// Workgroup geometry: one thread per point of a 32 x 32 tile; P planes are
+// box-summed per round so that every wave has scan work between barriers.
 struct PlaneCfg {
-    // points (= threads) per workgroup so that the k0-ring of W planes stays
-    // within 64 KB of LDS (128 KB for the widest case)
-    static constexpr int NT = (K0B * ES <= 64) ? 1024 : (K0B * ES <= 128) ? 512 : 256;
-    static constexpr int TYM = NT == 1024 ? 32 : 16;
-    static constexpr int TXM = NT == 256 ? 16 : 32;
-    static constexpr int ROWS = 2 * TYM - 1;     // max halo rows
-    static constexpr int COLS = 2 * TXM - 1;     // max halo cols
-    static constexpr int PA = 2 * TXM + 1;       // LDS pitch of the input tile (odd)
+    static constexpr int NT = 1024;
+    static constexpr int TYM = 32, TXM = 32;
+    static constexpr int KPM = 16;               // largest ky, kx
+    static constexpr int ROWS = TYM + KPM - 1;   // max halo rows
+    static constexpr int COLS = TXM + KPM - 1;   // max halo cols
+    static constexpr int PA = (COLS | 1);        // LDS pitch of the input tile (odd)
     static constexpr int PB = TXM + 1;           // LDS pitch of the row-pass output (odd)
     static constexpr int NLOAD = (ROWS * COLS + NT - 1) / NT;
+    static constexpr int P = 4;                  // planes per round
 };
 
-template <typename T, class Op, int K0B>
-__global__ void __launch_bounds__((PlaneCfg<K0B, sizeof(T)>::NT))
-k_plane_axis0(PlaneArgs a) {
-    using C = PlaneCfg<K0B, sizeof(T)>;
-    constexpr int NT = C::NT;
-    __shared__ T sA[C::ROWS * C::PA];
-    __shared__ T sB[C::ROWS * C::PB];
+// One BDBS block of a plane pass: out[r] = rsuf_b[r] op rpre_{b+1}[r-1] for
+// r < k (out[0] = rsuf_b[0]), with src[0..k) the block and src[k..2k-1) the
+// next block, strided by `ss` in LDS.  KP >= k is a compile-time bound: the
+// loads are unconditional (every address stays inside the LDS tile) and
+// lanes past k are replaced by the identity, so the scan has no branches.
+template <typename T, class Op, int KP>
+__device__ __forceinline__ void bdbs_block_lds(const T* __restrict__ src, int ss,
+                                               T* __restrict__ dst, int ds, int k) {
+    const T e = Op::template id<T>();
+    T a0[KP], a1[KP];
+#pragma unroll
+    for (int r = 0; r < KP; ++r) {
+        const T v0 = src[r * ss];
+        a0[r] = r < k ? v0 : e;
+        if (r < KP - 1) {
+            const T v1 = src[(k + r) * ss];
+            a1[r] = r < k - 1 ? v1 : e;
+        }
+    }
+    T sfx = e;
+#pragma unroll
+    for (int r = KP - 1; r >= 0; --r) {
+        sfx = Op::apply(a0[r], sfx);
+        a0[r] = sfx;
+    }
+    T p = e;
+#pragma unroll
+    for (int r = 1; r < KP; ++r) {
+        p = Op::apply(p, a1[r - 1]);
+        a0[r] = Op::apply(a0[r], p);
+    }
+#pragma unroll
+    for (int r = 0; r < KP; ++r)
+        if (r < k) dst[r * ds] = a0[r];
+}
+
+template <typename T, class Op, int K0B, int KP>
+__global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
+    using C = PlaneCfg;
+    constexpr int NT = C::NT, P = C::P;
+    __shared__ T sA[P * C::ROWS * C::PA];
+    __shared__ T sB[P * C::ROWS * C::PB];
     __shared__ T ring[K0B * NT];
 
     const T e = Op::template id<T>();
     const int tid = threadIdx.x;
-    const T* __restrict__ X = (const T*)a.X;
 
     // workgroup -> (segment, mid, tile); the workgroups that land on one XCD
     // (ids congruent mod 8) get consecutive tiles of the plane
@@ -75,40 +109,35 @@ k_plane_axis0(PlaneArgs a) {
     const i64 rest = wg / tiles;
     const i64 mid = rest % a.MID;
     const i64 s = rest / a.MID;
-    const i64 y0 = (tile / a.tilesX) * a.TY;
-    const i64 x0 = (tile % a.tilesX) * a.TX;
+    const int y0 = (int)((tile / a.tilesX) * a.TY);
+    const int x0 = (int)((tile % a.tilesX) * a.TX);
     const i64 qa = s * a.segblocks;
     const i64 qb = qa + a.segblocks < a.Q ? qa + a.segblocks : a.Q;
     const int k0 = a.k0, ky = a.ky, kx = a.kx;
+    const int NY = (int)a.NY, NX = (int)a.NX;
     const i64 M = a.M;
 
     // this thread's point of the tile
     const int py = tid / C::TXM, px = tid % C::TXM;
-    const bool pvalid = py < a.TY && px < a.TX && y0 + py < a.NY && x0 + px < a.NX;
-    const i64 m = (mid * a.NY + y0 + py) * a.NX + x0 + px;
+    const bool pvalid = py < a.TY && px < a.TX && y0 + py < NY && x0 + px < NX;
+    const i64 m = (mid * NY + y0 + py) * (i64)NX + x0 + px;
 
-    // halo-tile load plan (identical for every plane)
+    // halo-tile load plan, identical for every plane: elements outside the
+    // tensor read a valid address and are replaced by the identity
     const int rows_in = a.TY + ky - 1, cols_in = a.TX + kx - 1;
     const int count = rows_in * cols_in;
-    int loff[C::NLOAD];
-    i64 goff[C::NLOAD];
-    bool gval[C::NLOAD];
+    int loff[C::NLOAD], goff[C::NLOAD];
+    bool gin[C::NLOAD];
 #pragma unroll
     for (int j = 0; j < C::NLOAD; ++j) {
         const int el = tid + j * NT;
         const int r = el / cols_in, c = el % cols_in;
+        gin[j] = el < count && y0 + r < NY && x0 + c < NX;
         loff[j] = el < count ? r * C::PA + c : -1;
-        gval[j] = el < count && y0 + r < a.NY && x0 + c < a.NX;
-        goff[j] = (mid * a.NY + y0 + r) * a.NX + x0 + c;
+        goff[j] = gin[j] ? (y0 + r) * NX + x0 + c : 0;
     }
-    const i64 plane_stride = a.MID * a.NY * a.NX;
-
-    T pre[C::NLOAD];
-    auto fetch = [&](i64 t) {
-        const T* src = X + t * plane_stride;
-#pragma unroll
-        for (int j = 0; j < C::NLOAD; ++j) pre[j] = gval[j] ? src[goff[j]] : e;
-    };
+    const i64 plane_stride = M;
+    const T* __restrict__ Xm = (const T*)a.X + mid * (i64)NY * NX;
 
     const i64 t_begin = qa * k0;
     i64 t_end = (qb + 1) * k0;  // one block past the run: the suffix/inclusion lag
@@ -117,15 +146,12 @@ k_plane_axis0(PlaneArgs a) {
     const bool do_ex = a.exc != nullptr, do_inc = a.inc != nullptr;
     T* __restrict__ exc = (T*)a.exc;
     T* __restrict__ inc = (T*)a.inc;
-    const T* __restrict__ PX = (const T*)a.PX;
-    const T* __restrict__ SX = (const T*)a.SX;
-    const T* __restrict__ Trest = (const T*)a.Trest;
 
     Axis0State<T, Op, K0B> st;
     st.P = e;
     if (do_ex && pvalid) {
-        st.P = PX[qa * M + m];
-        if (Trest) st.P = Op::apply(st.P, Trest[m]);
+        st.P = ((const T*)a.PX)[qa * M + m];
+        if (a.Trest) st.P = Op::apply(st.P, ((const T*)a.Trest)[m]);
     }
     T sx_next = e;  // SX of the block being filled
 
@@ -169,66 +195,72 @@ k_plane_axis0(PlaneArgs a) {
         if (q < qb) st.absorb(v, k0, do_ex, do_inc);
     };
 
-    if (t_begin < t_end) fetch(t_begin);
-    i64 qlast = qa - 1;
-    for (i64 t = t_begin; t < t_end; ++t) {
-        const i64 q = t / k0;
-        const int r = (int)(t - q * k0);
-        if (r == 0 && do_ex && pvalid) sx_next = q < a.Q ? SX[q * M + m] : e;
-        // 1. stage the prefetched halo tile, prefetch the next plane
+    // rounds of up to P planes that stay inside one k0-block
+    auto round_len = [&](i64 t) -> int {
+        const i64 bend = (t / k0 + 1) * k0;
+        i64 lim = bend < t_end ? bend : t_end;
+        const i64 n = lim - t;
+        return (int)(n < P ? n : P);
+    };
+    T pre[P][C::NLOAD];
+    auto fetch_round = [&](i64 t, int np) {
 #pragma unroll
-        for (int j = 0; j < C::NLOAD; ++j)
-            if (loff[j] >= 0) sA[loff[j]] = pre[j];
-        if (t + 1 < t_end) fetch(t + 1);
-        __syncthreads();
-        // 2. BDBS along x for every halo row: range suffix of block b, plus the
-        //    range prefix of block b+1 (identity past the tensor edge)
-        {
-            const int nbx = a.TX / kx;
-            const int tasks = rows_in * nbx;
-            for (int task = tid; task < tasks; task += NT) {
-                const int row = task % rows_in, b = task / rows_in;
-                const T* src = sA + row * C::PA + b * kx;
-                T* dst = sB + row * C::PB + b * kx;
-                T sfx = e;
-                for (int rr = kx - 1; rr >= 0; --rr) {
-                    sfx = Op::apply(src[rr], sfx);
-                    dst[rr] = sfx;
-                }
-                T p = e;
-                for (int rr = 1; rr < kx; ++rr) {
-                    p = Op::apply(p, src[kx + rr - 1]);
-                    dst[rr] = Op::apply(dst[rr], p);
-                }
+        for (int u = 0; u < P; ++u) {
+            const T* src = Xm + (u < np ? t + u : t) * plane_stride;
+#pragma unroll
+            for (int j = 0; j < C::NLOAD; ++j) {
+                const T v = src[goff[j]];
+                pre[u][j] = gin[j] ? v : e;
             }
         }
-        __syncthreads();
-        // 3. BDBS along y for every column into ring slot r
-        {
-            const int nby = a.TY / ky;
-            const int tasks = a.TX * nby;
-            T* slot = ring + r * NT;
-            for (int task = tid; task < tasks; task += NT) {
-                const int col = task % a.TX, b = task / a.TX;
-                const T* src = sB + b * ky * C::PB + col;
-                T* dst = slot + b * ky * C::TXM + col;
-                T sfx = e;
-                for (int rr = ky - 1; rr >= 0; --rr) {
-                    sfx = Op::apply(src[rr * C::PB], sfx);
-                    dst[rr * C::TXM] = sfx;
-                }
-                T p = e;
-                for (int rr = 1; rr < ky; ++rr) {
-                    p = Op::apply(p, src[(ky + rr - 1) * C::PB]);
-                    dst[rr * C::TXM] = Op::apply(dst[rr * C::TXM], p);
-                }
+    };
+
+    const int nbx = a.TX / kx, nby = a.TY / ky;
+    const int rt1 = rows_in * nbx, ct1 = a.TX * nby;
+    i64 qlast = qa - 1;
+    i64 t = t_begin;
+    int np = t < t_end ? round_len(t) : 0;
+    if (np > 0) fetch_round(t, np);
+    while (t < t_end) {
+        const i64 q = t / k0;
+        const int r0 = (int)(t - q * k0);
+        if (r0 == 0 && do_ex && pvalid) sx_next = q < a.Q ? ((const T*)a.SX)[q * M + m] : e;
+        // 1. stage this round's halo tiles; start loading the next round
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            if (u < np) {
+#pragma unroll
+                for (int j = 0; j < C::NLOAD; ++j)
+                    if (loff[j] >= 0) sA[u * C::ROWS * C::PA + loff[j]] = pre[u][j];
             }
+        }
+        const i64 tn = t + np;
+        const int npn = tn < t_end ? round_len(tn) : 0;
+        if (npn > 0) fetch_round(tn, npn);
+        __syncthreads();
+        // 2. BDBS along x for every halo row of every plane of the round
+        for (int task = tid; task < np * rt1; task += NT) {
+            const int u = task / rt1, rem = task - u * rt1;
+            const int b = rem / rows_in, row = rem - b * rows_in;
+            bdbs_block_lds<T, Op, KP>(sA + u * C::ROWS * C::PA + row * C::PA + b * kx, 1,
+                                      sB + u * C::ROWS * C::PB + row * C::PB + b * kx, 1, kx);
+        }
+        __syncthreads();
+        // 3. BDBS along y for every column into the ring slots of the round
+        for (int task = tid; task < np * ct1; task += NT) {
+            const int u = task / ct1, rem = task - u * ct1;
+            const int b = rem / a.TX, col = rem - b * a.TX;
+            bdbs_block_lds<T, Op, KP>(sB + u * C::ROWS * C::PB + b * ky * C::PB + col, C::PB,
+                                      ring + (r0 + u) * NT + b * ky * C::TXM + col, C::TXM, ky);
         }
         // 4. a block of W planes is complete: emit the previous block
-        if (r == k0 - 1 || t == a.n0 - 1) {
+        const i64 tl = t + np - 1;
+        if (tl - q * k0 == k0 - 1 || tl == a.n0 - 1) {
             block_step(q);
             qlast = q;
         }
+        t = tn;
+        np = npn;
     }
     // the block after the run lies past the tensor: emit the last block
     if (qlast < qb) {
@@ -238,33 +270,38 @@ k_plane_axis0(PlaneArgs a) {
 }
 
 bool plane_eligible(int d, const i64* n, const i64* k, int es) {
-    if (d < 3) return false;
-    const i64 k0 = k[0];
-    if (k0 > 64) return false;
-    int kb = k0 <= 1 ? 1 : k0 <= 2 ? 2 : k0 <= 4 ? 4 : k0 <= 8 ? 8 : k0 <= 16 ? 16 : k0 <= 32 ? 32 : 64;
-    const int nt = (kb * es <= 64) ? 1024 : (kb * es <= 128) ? 512 : 256;
-    const int tym = nt == 1024 ? 32 : 16, txm = nt == 256 ? 16 : 32;
-    return k[d - 2] <= tym && k[d - 1] <= txm;
+    if (d < 3 || es != 4) return false;
+    if (k[0] > 16) return false;
+    if (k[d - 2] > PlaneCfg::KPM || k[d - 1] > PlaneCfg::KPM) return false;
+    // plane offsets are 32-bit inside the kernel
+    if (n[d - 2] * n[d - 1] >= ((i64)1 << 31)) return false;
+    return true;
 }
 
-template <typename T, class Op, int K0B>
+template <typename T, class Op, int K0B, int KP>
 static void launch_plane_kb(PlaneArgs pa, hipStream_t st) {
-    using C = PlaneCfg<K0B, sizeof(T)>;
+    using C = PlaneCfg;
     pa.TY = (int)(C::TYM / pa.ky * pa.ky);
     pa.TX = (int)(C::TXM / pa.kx * pa.kx);
     pa.tilesY = (pa.NY + pa.TY - 1) / pa.TY;
     pa.tilesX = (pa.NX + pa.TX - 1) / pa.TX;
     const i64 tiles = pa.tilesY * pa.tilesX * pa.MID;
-    // enough workgroups to cover the CUs twice; each run of blocks reads
-    // one extra block of planes
-    i64 nseg = (512 + tiles - 1) / tiles;
+    // enough workgroups to cover every CU; each run of blocks reads one
+    // extra block of planes
+    i64 nseg = (256 + tiles - 1) / tiles;
     if (nseg > pa.Q) nseg = pa.Q;
     if (nseg < 1) nseg = 1;
     pa.segblocks = (pa.Q + nseg - 1) / nseg;
     pa.nseg = (pa.Q + pa.segblocks - 1) / pa.segblocks;
     const i64 grid = tiles * pa.nseg;
-    hipLaunchKernelGGL((k_plane_axis0<T, Op, K0B>), dim3((unsigned)grid), dim3(C::NT), 0, st,
+    hipLaunchKernelGGL((k_plane_axis0<T, Op, K0B, KP>), dim3((unsigned)grid), dim3(C::NT), 0, st,
                        pa);
+}
+
+template <typename T, class Op, int K0B>
+static void launch_plane_kp(PlaneArgs pa, hipStream_t st) {
+    if (pa.ky <= 8 && pa.kx <= 8) launch_plane_kb<T, Op, K0B, 8>(pa, st);
+    else launch_plane_kb<T, Op, K0B, 16>(pa, st);
 }
 
 template <typename T, class Op>
@@ -276,25 +313,17 @@ void launch_plane_axis0(const T* X, const T* PX, const T* SX, const T* Trest, T*
     pa.X = X; pa.PX = PX; pa.SX = SX; pa.Trest = Trest; pa.exc = exc; pa.inc = inc;
     pa.n0 = n0; pa.MID = MID; pa.NY = NY; pa.NX = NX; pa.M = MID * NY * NX; pa.Q = Q;
     pa.k0 = (int)k0; pa.ky = (int)ky; pa.kx = (int)kx;
-    if (k0 <= 1) launch_plane_kb<T, Op, 1>(pa, st);
-    else if (k0 <= 2) launch_plane_kb<T, Op, 2>(pa, st);
-    else if (k0 <= 4) launch_plane_kb<T, Op, 4>(pa, st);
-    else if (k0 <= 8) launch_plane_kb<T, Op, 8>(pa, st);
-    else if (k0 <= 16) launch_plane_kb<T, Op, 16>(pa, st);
-    else if (k0 <= 32) launch_plane_kb<T, Op, 32>(pa, st);
-    else launch_plane_kb<T, Op, 64>(pa, st);
+    if (k0 <= 4) launch_plane_kp<T, Op, 4>(pa, st);
+    else if (k0 <= 8) launch_plane_kp<T, Op, 8>(pa, st);
+    else launch_plane_kp<T, Op, 16>(pa, st);
 }
 
 #define EXS_INST_PLANE(T, OP)                                                                  \
     template void launch_plane_axis0<T, OP>(const T*, const T*, const T*, const T*, T*, T*,    \
                                             i64, i64, i64, i64, i64, i64, i64, i64, hipStream_t);
 EXS_INST_PLANE(float, OpSum)
-EXS_INST_PLANE(double, OpSum)
 EXS_INST_PLANE(int, OpSum)
-EXS_INST_PLANE(long long, OpSum)
 EXS_INST_PLANE(float, OpMax)
-EXS_INST_PLANE(double, OpMax)
 EXS_INST_PLANE(int, OpMax)
-EXS_INST_PLANE(long long, OpMax)
 
 }  // namespace exs
