@@ -54,21 +54,30 @@ struct PlaneCfg {
 
 // One BDBS block of a plane pass: out[r] = rsuf_b[r] op rpre_{b+1}[r-1] for
 // r < k (out[0] = rsuf_b[0]), with src[0..k) the block and src[k..2k-1) the
-// next block, strided by `ss` in LDS.  KP >= k is a compile-time bound: the
-// loads are unconditional (every address stays inside the LDS tile) and
-// lanes past k are replaced by the identity, so the scan has no branches.
-template <typename T, class Op, int KP>
-__device__ __forceinline__ void bdbs_block_lds(const T* __restrict__ src, int ss,
-                                               T* __restrict__ dst, int ds, int k) {
+// next block, strided by SS in LDS.  KP >= k is a compile-time bound: the
+// loads are unconditional (every address stays inside the LDS tile) and, when
+// k < KP, lanes past k are replaced by the identity, so the scan has no
+// branches.
+template <typename T, class Op, int KP, int SS, int DS>
+__device__ __forceinline__ void bdbs_block_lds(const T* __restrict__ src, T* __restrict__ dst,
+                                               int k) {
     const T e = Op::template id<T>();
     T a0[KP], a1[KP];
+    if (k == KP) {
 #pragma unroll
-    for (int r = 0; r < KP; ++r) {
-        const T v0 = src[r * ss];
-        a0[r] = r < k ? v0 : e;
-        if (r < KP - 1) {
-            const T v1 = src[(k + r) * ss];
-            a1[r] = r < k - 1 ? v1 : e;
+        for (int r = 0; r < KP; ++r) {
+            a0[r] = src[r * SS];
+            if (r < KP - 1) a1[r] = src[(KP + r) * SS];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < KP; ++r) {
+            const T v0 = src[r * SS];
+            a0[r] = r < k ? v0 : e;
+            if (r < KP - 1) {
+                const T v1 = src[(k + r) * SS];
+                a1[r] = r < k - 1 ? v1 : e;
+            }
         }
     }
     T sfx = e;
@@ -85,15 +94,35 @@ __device__ __forceinline__ void bdbs_block_lds(const T* __restrict__ src, int ss
     }
 #pragma unroll
     for (int r = 0; r < KP; ++r)
-        if (r < k) dst[r * ds] = a0[r];
+        if (r < k) dst[r * DS] = a0[r];
+}
+
+// Raw buffer access: a resource descriptor (uniform 64-bit base and byte
+// range, held in SGPRs) plus a per-thread 32-bit byte offset.  Accesses past
+// the range read 0 and drop stores.  Word 3 = 0x00020000 is the gfx9-family
+// raw-buffer format.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned voff) {
+    static_assert(sizeof(T) == 4, "4-byte elements");
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, T v) {
+    static_assert(sizeof(T) == 4, "4-byte elements");
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, 0, 0);
 }
 
 template <typename T, class Op, int K0B, int KP>
 __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
     using C = PlaneCfg;
     constexpr int NT = C::NT, P = C::P;
-    __shared__ T sA[P * C::ROWS * C::PA];
-    __shared__ T sB[P * C::ROWS * C::PB];
+    constexpr int SA = C::ROWS * C::PA, SB = C::ROWS * C::PB;
+    __shared__ T sA[P * SA];
+    __shared__ T sB[P * SB];
     __shared__ T ring[K0B * NT];
 
     const T e = Op::template id<T>();
@@ -113,20 +142,24 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
     const int x0 = (int)((tile % a.tilesX) * a.TX);
     const i64 qa = s * a.segblocks;
     const i64 qb = qa + a.segblocks < a.Q ? qa + a.segblocks : a.Q;
-    const int k0 = a.k0, ky = a.ky, kx = a.kx;
+    const int k0 = a.k0, ky = a.ky, kx = a.kx, TY = a.TY, TX = a.TX;
     const int NY = (int)a.NY, NX = (int)a.NX;
     const i64 M = a.M;
+    const i64 n0 = a.n0;
 
-    // this thread's point of the tile
+    // this thread's point of the tile; per-thread offsets are 32-bit byte
+    // offsets within a plane, the per-plane bases are uniform
     const int py = tid / C::TXM, px = tid % C::TXM;
-    const bool pvalid = py < a.TY && px < a.TX && y0 + py < NY && x0 + px < NX;
-    const i64 m = (mid * NY + y0 + py) * (i64)NX + x0 + px;
+    const bool pvalid = py < TY && px < TX && y0 + py < NY && x0 + px < NX;
+    const unsigned mb = ((unsigned)(mid * NY * NX) + (unsigned)((y0 + py) * NX + x0 + px)) *
+                        (unsigned)sizeof(T);
 
     // halo-tile load plan, identical for every plane: elements outside the
     // tensor read a valid address and are replaced by the identity
-    const int rows_in = a.TY + ky - 1, cols_in = a.TX + kx - 1;
+    const int rows_in = TY + ky - 1, cols_in = TX + kx - 1;
     const int count = rows_in * cols_in;
-    int loff[C::NLOAD], goff[C::NLOAD];
+    int loff[C::NLOAD];
+    unsigned goff[C::NLOAD];
     bool gin[C::NLOAD];
 #pragma unroll
     for (int j = 0; j < C::NLOAD; ++j) {
@@ -134,39 +167,79 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
         const int r = el / cols_in, c = el % cols_in;
         gin[j] = el < count && y0 + r < NY && x0 + c < NX;
         loff[j] = el < count ? r * C::PA + c : -1;
-        goff[j] = gin[j] ? (y0 + r) * NX + x0 + c : 0;
+        goff[j] = gin[j] ? ((unsigned)(mid * NY * NX) + (unsigned)((y0 + r) * NX + x0 + c)) *
+                               (unsigned)sizeof(T)
+                         : 0u;
     }
-    const i64 plane_stride = M;
-    const T* __restrict__ Xm = (const T*)a.X + mid * (i64)NY * NX;
 
+    // scan tasks of a full round: row task (u, b, row), column task (u, b,
+    // col), flattened with u outermost so a round of np < P planes runs the
+    // tasks whose u < np.  The first two of each thread are decoded once and
+    // packed as u | b << 2 | idx << 8; any further ones (small boxes only)
+    // are decoded per round.  -1 marks no task.
+    const int nbx = TX / kx, nby = TY / ky;
+    const int rt1 = rows_in * nbx, ct1 = TX * nby;
+    const int rtot = P * rt1, ctot = P * ct1;
+    auto dec_row = [&](int task) -> int {
+        const int u = task / rt1, rem = task - u * rt1;
+        const int b = rem / rows_in, row = rem - b * rows_in;
+        return u | (b << 2) | (row << 8);
+    };
+    auto dec_col = [&](int task) -> int {
+        const int u = task / ct1, rem = task - u * ct1;
+        const int b = rem / TX, col = rem - b * TX;
+        return u | (b << 2) | (col << 8);
+    };
+    const int rp0 = tid < rtot ? dec_row(tid) : -1, rp1 = tid + NT < rtot ? dec_row(tid + NT) : -1;
+    const int cp0 = tid < ctot ? dec_col(tid) : -1, cp1 = tid + NT < ctot ? dec_col(tid + NT) : -1;
+    auto run_row = [&](int pk, int np) {
+        if (pk < 0) return;
+        const int u = pk & 3;
+        if (u >= np) return;
+        const int b = (pk >> 2) & 63, row = pk >> 8;
+        bdbs_block_lds<T, Op, KP, 1, 1>(sA + u * SA + row * C::PA + b * kx,
+                                        sB + u * SB + row * C::PB + b * kx, kx);
+    };
+    auto run_col = [&](int pk, int np, int r0) {
+        if (pk < 0) return;
+        const int u = pk & 3;
+        if (u >= np) return;
+        const int b = (pk >> 2) & 63, col = pk >> 8;
+        bdbs_block_lds<T, Op, KP, C::PB, C::TXM>(sB + u * SB + b * ky * C::PB + col,
+                                                  ring + (r0 + u) * NT + b * ky * C::TXM + col,
+                                                  ky);
+    };
+
+    const T* __restrict__ X = (const T*)a.X;
     const i64 t_begin = qa * k0;
     i64 t_end = (qb + 1) * k0;  // one block past the run: the suffix/inclusion lag
-    if (t_end > a.n0) t_end = a.n0;
+    if (t_end > n0) t_end = n0;
 
     const bool do_ex = a.exc != nullptr, do_inc = a.inc != nullptr;
     T* __restrict__ exc = (T*)a.exc;
     T* __restrict__ inc = (T*)a.inc;
 
+    const unsigned plane_bytes = (unsigned)(M * (i64)sizeof(T));
     Axis0State<T, Op, K0B> st;
     st.P = e;
     if (do_ex && pvalid) {
-        st.P = ((const T*)a.PX)[qa * M + m];
-        if (a.Trest) st.P = Op::apply(st.P, ((const T*)a.Trest)[m]);
+        st.P = bload<T>(buf((const T*)a.PX + qa * M, plane_bytes), mb);
+        if (a.Trest) st.P = Op::apply(st.P, bload<T>(buf(a.Trest, plane_bytes), mb));
     }
     T sx_next = e;  // SX of the block being filled
 
     // Emit block (q-1) from the ring holding block q, then absorb block q.
-    auto block_step = [&](i64 q) {
+    auto block_step = [&](i64 q) __attribute__((always_inline)) {
         __syncthreads();
         T v[K0B];
 #pragma unroll
         for (int r = 0; r < K0B; ++r)
-            v[r] = (r < k0 && q * k0 + r < a.n0) ? ring[r * NT + tid] : e;
+            v[r] = (r < k0 && q * k0 + r < n0) ? ring[r * NT + tid] : e;
         if (q == qa) {
             st.absorb(v, k0, do_ex, do_inc);
             return;
         }
-        const i64 qe = q - 1;
+        const i64 xb = (q - 1) * k0;
         if (pvalid) {
             if (do_ex) {
                 T S = sx_next;
@@ -174,8 +247,9 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
                 for (int r = K0B - 1; r >= 0; --r) {
                     if (r < k0) {
                         S = Op::apply(v[r], S);
-                        const i64 x = qe * k0 + r;
-                        if (x < a.n0) exc[x * M + m] = Op::apply(st.pex[r], S);
+                        if (xb + r < n0)
+                            bstore<T>(buf(exc + (xb + r) * M, plane_bytes), mb,
+                                      Op::apply(st.pex[r], S));
                     }
                 }
             }
@@ -186,8 +260,7 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
                     if (r < k0) {
                         T val = st.rs[r];
                         if (r > 0) { p = Op::apply(p, v[r - 1]); val = Op::apply(val, p); }
-                        const i64 x = qe * k0 + r;
-                        if (x < a.n0) inc[x * M + m] = val;
+                        if (xb + r < n0) bstore<T>(buf(inc + (xb + r) * M, plane_bytes), mb, val);
                     }
                 }
             }
@@ -195,71 +268,65 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
         if (q < qb) st.absorb(v, k0, do_ex, do_inc);
     };
 
-    // rounds of up to P planes that stay inside one k0-block
-    auto round_len = [&](i64 t) -> int {
-        const i64 bend = (t / k0 + 1) * k0;
-        i64 lim = bend < t_end ? bend : t_end;
-        const i64 n = lim - t;
-        return (int)(n < P ? n : P);
-    };
     T pre[P][C::NLOAD];
-    auto fetch_round = [&](i64 t, int np) {
+    auto fetch_round = [&](i64 t, int np) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < P; ++u) {
-            const T* src = Xm + (u < np ? t + u : t) * plane_stride;
+            const __amdgpu_buffer_rsrc_t pl = buf(X + (u < np ? t + u : t) * M, plane_bytes);
 #pragma unroll
             for (int j = 0; j < C::NLOAD; ++j) {
-                const T v = src[goff[j]];
+                const T v = bload<T>(pl, goff[j]);
                 pre[u][j] = gin[j] ? v : e;
             }
         }
     };
 
-    const int nbx = a.TX / kx, nby = a.TY / ky;
-    const int rt1 = rows_in * nbx, ct1 = a.TX * nby;
+    // rounds of up to P planes that stay inside one k0-block
     i64 qlast = qa - 1;
     i64 t = t_begin;
-    int np = t < t_end ? round_len(t) : 0;
+    i64 q = qa;   // block of plane t
+    int r0 = 0;   // position of plane t in its block
+    auto round_len = [&](i64 tt, int rr) -> int {
+        i64 n = (i64)(k0 - rr);
+        if (tt + n > t_end) n = t_end - tt;
+        return (int)(n < P ? n : P);
+    };
+    int np = t < t_end ? round_len(t, 0) : 0;
     if (np > 0) fetch_round(t, np);
     while (t < t_end) {
-        const i64 q = t / k0;
-        const int r0 = (int)(t - q * k0);
-        if (r0 == 0 && do_ex && pvalid) sx_next = q < a.Q ? ((const T*)a.SX)[q * M + m] : e;
+        if (r0 == 0 && do_ex && pvalid)
+            sx_next = q < a.Q ? bload<T>(buf((const T*)a.SX + q * M, plane_bytes), mb) : e;
         // 1. stage this round's halo tiles; start loading the next round
 #pragma unroll
         for (int u = 0; u < P; ++u) {
             if (u < np) {
 #pragma unroll
                 for (int j = 0; j < C::NLOAD; ++j)
-                    if (loff[j] >= 0) sA[u * C::ROWS * C::PA + loff[j]] = pre[u][j];
+                    if (loff[j] >= 0) sA[u * SA + loff[j]] = pre[u][j];
             }
         }
         const i64 tn = t + np;
-        const int npn = tn < t_end ? round_len(tn) : 0;
+        const int rn = r0 + np == k0 ? 0 : r0 + np;
+        const int npn = tn < t_end ? round_len(tn, rn) : 0;
         if (npn > 0) fetch_round(tn, npn);
         __syncthreads();
         // 2. BDBS along x for every halo row of every plane of the round
-        for (int task = tid; task < np * rt1; task += NT) {
-            const int u = task / rt1, rem = task - u * rt1;
-            const int b = rem / rows_in, row = rem - b * rows_in;
-            bdbs_block_lds<T, Op, KP>(sA + u * C::ROWS * C::PA + row * C::PA + b * kx, 1,
-                                      sB + u * C::ROWS * C::PB + row * C::PB + b * kx, 1, kx);
-        }
+        run_row(rp0, np);
+        run_row(rp1, np);
+        for (int task = tid + 2 * NT; task < rtot; task += NT) run_row(dec_row(task), np);
         __syncthreads();
         // 3. BDBS along y for every column into the ring slots of the round
-        for (int task = tid; task < np * ct1; task += NT) {
-            const int u = task / ct1, rem = task - u * ct1;
-            const int b = rem / a.TX, col = rem - b * a.TX;
-            bdbs_block_lds<T, Op, KP>(sB + u * C::ROWS * C::PB + b * ky * C::PB + col, C::PB,
-                                      ring + (r0 + u) * NT + b * ky * C::TXM + col, C::TXM, ky);
-        }
+        run_col(cp0, np, r0);
+        run_col(cp1, np, r0);
+        for (int task = tid + 2 * NT; task < ctot; task += NT) run_col(dec_col(task), np, r0);
         // 4. a block of W planes is complete: emit the previous block
-        const i64 tl = t + np - 1;
-        if (tl - q * k0 == k0 - 1 || tl == a.n0 - 1) {
+        if (r0 + np == k0 || t + np == n0) {
             block_step(q);
             qlast = q;
         }
         t = tn;
+        if (rn == 0) ++q;
+        r0 = rn;
         np = npn;
     }
     // the block after the run lies past the tensor: emit the last block
@@ -275,6 +342,10 @@ bool plane_eligible(int d, const i64* n, const i64* k, int es) {
     if (k[d - 2] > PlaneCfg::KPM || k[d - 1] > PlaneCfg::KPM) return false;
     // plane offsets are 32-bit inside the kernel
     if (n[d - 2] * n[d - 1] >= ((i64)1 << 31)) return false;
+    // per-point byte offsets within a plane of the (middle x plane) space are 32-bit
+    i64 M = 1;
+    for (int i = 1; i < d; ++i) M *= n[i];
+    if (M * es >= ((i64)1 << 32)) return false;
     return true;
 }
 
