@@ -226,7 +226,11 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
         st.P = bload<T>(buf((const T*)a.PX + qa * M, plane_bytes), mb);
         if (a.Trest) st.P = Op::apply(st.P, bload<T>(buf(a.Trest, plane_bytes), mb));
     }
-    T sx_next = e;  // SX of the block being filled
+    // SX of the block being filled, loaded when the block starts (from an
+    // in-range block index; blocks past the last one use the identity at the
+    // point of use, so the register is never overwritten while in flight)
+    T sx_raw = e;
+    bool sx_valid = false;
 
     // Emit block (q-1) from the ring holding block q, then absorb block q.
     auto block_step = [&](i64 q) __attribute__((always_inline)) {
@@ -242,7 +246,7 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
         const i64 xb = (q - 1) * k0;
         if (pvalid) {
             if (do_ex) {
-                T S = sx_next;
+                T S = sx_valid ? sx_raw : e;
 #pragma unroll
                 for (int r = K0B - 1; r >= 0; --r) {
                     if (r < k0) {
@@ -268,16 +272,15 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
         if (q < qb) st.absorb(v, k0, do_ex, do_inc);
     };
 
+    // raw prefetched values; the identity for elements outside the tensor is
+    // applied when they are staged, so no load is consumed early
     T pre[P][C::NLOAD];
     auto fetch_round = [&](i64 t, int np) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < P; ++u) {
             const __amdgpu_buffer_rsrc_t pl = buf(X + (u < np ? t + u : t) * M, plane_bytes);
 #pragma unroll
-            for (int j = 0; j < C::NLOAD; ++j) {
-                const T v = bload<T>(pl, goff[j]);
-                pre[u][j] = gin[j] ? v : e;
-            }
+            for (int j = 0; j < C::NLOAD; ++j) pre[u][j] = bload<T>(pl, goff[j]);
         }
     };
 
@@ -294,15 +297,19 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
     int np = t < t_end ? round_len(t, 0) : 0;
     if (np > 0) fetch_round(t, np);
     while (t < t_end) {
-        if (r0 == 0 && do_ex && pvalid)
-            sx_next = q < a.Q ? bload<T>(buf((const T*)a.SX + q * M, plane_bytes), mb) : e;
+        if (r0 == 0) {
+            sx_valid = q < a.Q;
+            if (do_ex)
+                sx_raw = bload<T>(buf((const T*)a.SX + (q < a.Q ? q : a.Q - 1) * M, plane_bytes),
+                                  mb);
+        }
         // 1. stage this round's halo tiles; start loading the next round
 #pragma unroll
         for (int u = 0; u < P; ++u) {
             if (u < np) {
 #pragma unroll
                 for (int j = 0; j < C::NLOAD; ++j)
-                    if (loff[j] >= 0) sA[u * SA + loff[j]] = pre[u][j];
+                    if (loff[j] >= 0) sA[u * SA + loff[j]] = gin[j] ? pre[u][j] : e;
             }
         }
         const i64 tn = t + np;
@@ -331,7 +338,7 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
     }
     // the block after the run lies past the tensor: emit the last block
     if (qlast < qb) {
-        if (do_ex && pvalid) sx_next = e;
+        sx_valid = false;
         block_step(qb);
     }
 }
