@@ -134,6 +134,17 @@ struct Axis0State {
     T rs[K0B];    // range suffix of the current block (Inc)
     T P;          // op of everything before the next block (incl. Trest)
 
+    // Absorb a block whose values past k0 are the identity (no masks needed:
+    // an identity leaves the running prefix and the suffix unchanged).
+    __device__ __forceinline__ void absorb_all(const T (&v)[K0B]) {
+        const T e = Op::template id<T>();
+#pragma unroll
+        for (int r = 0; r < K0B; ++r) { pex[r] = P; P = Op::apply(P, v[r]); }
+        T s = e;
+#pragma unroll
+        for (int r = K0B - 1; r >= 0; --r) { s = Op::apply(v[r], s); rs[r] = s; }
+    }
+
     // Absorb block values v[0..k0) as the new current block.
     __device__ __forceinline__ void absorb(const T (&v)[K0B], int k0, bool do_ex, bool do_inc) {
         const T e = Op::template id<T>();

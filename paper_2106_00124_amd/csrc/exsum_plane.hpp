@@ -1,0 +1,377 @@
+// exsum_plane.hpp -- fused streaming kernel for the first dimension-reduction
+// step of included/excluded sums on gfx950 (template; instantiated per element
+// type in exsum_plane_*.hip).
+//
+// Paper: Xu, Fraser, Leiserson, "Multidimensional Included and Excluded Sums"
+// (SIAM ACDA 2021, arXiv 2106.00124).
+//
+// For a rank >= 3 tensor viewed as (n0, MID, NY, NX) -- MID collects the
+// middle axes, already box-summed -- one workgroup owns a tile of the
+// (NY, NX) plane for a run of k0-blocks of axis 0 and walks axis 0, P planes
+// per round:
+//   1. the tiles plus their (ky-1, kx-1) halos are staged in LDS;
+//   2. BDBS along x over every halo row (Sec. 3: range suffix of a block,
+//      range prefix of the next block, combine);
+//   3. BDBS along y over every column, into a ring of k0 planes in LDS:
+//      W = each plane box-summed over its two axes ("BDBS-Along-Dim", Sec. 5);
+//   4. once a k0-block of W planes is in the ring, each thread (one point of
+//      the tile) updates its axis-0 state in registers and emits the previous
+//      block: the excluded sum (prefix before x0, suffix from x0+k0, the
+//      lower-dimensional contribution) and the included sum (BDBS along
+//      axis 0).
+//
+// Blocked layout.  Along y and x, every k-block of the tile (and of its halo)
+// occupies KP slots in LDS, KP the power of two >= k; the slots past k hold
+// the identity (written once), so every scan is a fixed-length KP scan with no
+// masks: the identities leave the range suffixes and prefixes of the real
+// elements unchanged.  Points of the tile use the same layout; padding points
+// are simply not stored.
+#pragma once
+#include "exsum_device.hpp"
+#include "exsum_internal.hpp"
+
+namespace exs {
+
+struct PlaneArgs {
+    const void* X;      // (n0, MID, NY, NX): input box-summed over the middle axes
+    const void* PX;     // (Q, M) op of W-block totals strictly before each block
+    const void* SX;     // (Q, M) op of W-block totals strictly after each block
+    const void* Trest;  // (M) lower-dimensional excluded sums, or null
+    void* exc;          // (n0, M) or null
+    void* inc;          // (n0, M) or null
+    i64 n0, MID, NY, NX, M, Q;
+    int k0, ky, kx;
+    i64 tilesY, tilesX, segblocks, nseg;
+};
+
+// 32 x 32 blocked points per workgroup, one thread each; P planes per round.
+template <int KP>
+struct PlaneCfg {
+    static constexpr int NT = 1024;
+    static constexpr int TYM = 32, TXM = 32;
+    static constexpr int NBY = TYM / KP, NBX = TXM / KP;   // output blocks per tile
+    static constexpr int ROWS = (NBY + 1) * KP;            // blocked halo rows
+    static constexpr int COLS = (NBX + 1) * KP;            // blocked halo cols
+    static constexpr int PA = COLS | 1;                    // odd LDS pitch
+    static constexpr int PB = TXM + 1;                     // odd LDS pitch
+    static constexpr int SA = ROWS * PA, SB = ROWS * PB;
+    static constexpr int MAXIN = (TYM + 15) * (TXM + 15);  // real halo elements, k <= 16
+    static constexpr int NLOAD = (MAXIN + NT - 1) / NT;
+    static constexpr int P = 4;
+    static constexpr int RT = (P * ROWS * NBX + NT - 1) / NT;  // row tasks per thread
+    static constexpr int CT = (P * TXM * NBY + NT - 1) / NT;   // column tasks per thread
+};
+
+// One BDBS block over KP slots: out[r] = rsuf_b[r] op rpre_{b+1}[r-1]
+// (out[0] = rsuf_b[0]); src[0..KP) is the block, src[KP..2KP-1) the next one,
+// strided by SS in LDS.  Loads issue back to back; no branches.
+template <typename T, class Op, int KP, int SS, int DS>
+__device__ __forceinline__ void bdbs_block(const T* __restrict__ src, T* __restrict__ dst) {
+    const T e = Op::template id<T>();
+    T a0[KP], a1[KP];
+#pragma unroll
+    for (int r = 0; r < KP; ++r) a0[r] = src[r * SS];
+#pragma unroll
+    for (int r = 0; r < KP - 1; ++r) a1[r] = src[(KP + r) * SS];
+    T sfx = e;
+#pragma unroll
+    for (int r = KP - 1; r >= 0; --r) {
+        sfx = Op::apply(a0[r], sfx);
+        a0[r] = sfx;
+    }
+    T p = e;
+#pragma unroll
+    for (int r = 1; r < KP; ++r) {
+        p = Op::apply(p, a1[r - 1]);
+        a0[r] = Op::apply(a0[r], p);
+    }
+#pragma unroll
+    for (int r = 0; r < KP; ++r) dst[r * DS] = a0[r];
+}
+
+// Raw buffer access: a descriptor (uniform 64-bit base and byte range, in
+// SGPRs) plus a per-thread 32-bit byte offset.  Accesses past the range read
+// 0 and drop stores.  Word 3 = 0x00020000 is the gfx9-family raw format.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned voff) {
+    static_assert(sizeof(T) == 4, "4-byte elements");
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, T v) {
+    static_assert(sizeof(T) == 4, "4-byte elements");
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, 0, 0);
+}
+
+template <typename T, class Op, int K0B, int KP>
+__global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
+    using C = PlaneCfg<KP>;
+    constexpr int NT = C::NT, P = C::P, SA = C::SA, SB = C::SB;
+    __shared__ T sA[P * SA + 1];  // + a dummy word for writes that must land nowhere
+    __shared__ T sB[P * SB];
+    __shared__ T ring[K0B * NT];
+
+    const T e = Op::template id<T>();
+    const int tid = threadIdx.x;
+
+    // workgroup -> (segment, mid, tile); the workgroups that land on one XCD
+    // (ids congruent mod 8) get consecutive tiles of the plane
+    i64 wg = blockIdx.x;
+    const i64 nwg = (i64)gridDim.x;
+    if ((nwg & 7) == 0) wg = (wg & 7) * (nwg >> 3) + (wg >> 3);
+    const i64 tiles = a.tilesY * a.tilesX;
+    const i64 tile = wg % tiles;
+    const i64 rest = wg / tiles;
+    const int mid = (int)(rest % a.MID);
+    const int seg = (int)(rest / a.MID);
+    const int k0 = a.k0, ky = a.ky, kx = a.kx;
+    const int NY = (int)a.NY, NX = (int)a.NX;
+    const int y0 = (int)(tile / a.tilesX) * (C::NBY * ky);
+    const int x0 = (int)(tile % a.tilesX) * (C::NBX * kx);
+    // plane and block indices fit in 32 bits (checked by the planner)
+    const int Qn = (int)a.Q;
+    const int qa = seg * (int)a.segblocks;
+    const int qb = qa + (int)a.segblocks < Qn ? qa + (int)a.segblocks : Qn;
+    const int n0 = (int)a.n0;
+    const i64 M = a.M;
+    const unsigned plane_bytes = (unsigned)(M * (i64)sizeof(T));
+    const unsigned mid_off = (unsigned)mid * (unsigned)NY * (unsigned)NX;
+
+    // this thread's point in the blocked tile
+    const int pyb = tid / C::TXM, pxb = tid % C::TXM;
+    const int py = (pyb / KP) * ky + pyb % KP, px = (pxb / KP) * kx + pxb % KP;
+    const bool pvalid = pyb % KP < ky && pxb % KP < kx && y0 + py < NY && x0 + px < NX;
+    // a point outside the tensor reads and writes past every descriptor's
+    // range: its loads return 0 and its stores are dropped
+    const unsigned mb = pvalid ? (mid_off + (unsigned)((y0 + py) * NX + x0 + px)) * sizeof(T)
+                               : (unsigned)K0B * plane_bytes;
+
+    // LDS: identity everywhere in the plane buffers, then per plane only the
+    // real halo elements are overwritten
+    for (int i = tid; i < P * SA; i += NT) sA[i] = e;
+    for (int r = 0; r < K0B; ++r) ring[r * NT + tid] = e;
+
+    // halo load plan (same for every plane): real element el -> (row, col) of
+    // the halo, its blocked LDS slot and its byte offset in a plane
+    const int rows_in = C::NBY * ky + ky - 1, cols_in = C::NBX * kx + kx - 1;
+    const int count = rows_in * cols_in;
+    int loff[C::NLOAD];
+    unsigned goff[C::NLOAD];
+#pragma unroll
+    for (int j = 0; j < C::NLOAD; ++j) {
+        const int el = tid + j * NT;
+        const int r = el / cols_in, c = el % cols_in;
+        const bool inside = el < count && y0 + r < NY && x0 + c < NX;
+        loff[j] = inside ? ((r / ky) * KP + r % ky) * C::PA + (c / kx) * KP + c % kx : P * SA;
+        goff[j] = inside ? (mid_off + (unsigned)((y0 + r) * NX + x0 + c)) * sizeof(T) : 0u;
+    }
+
+    // scan tasks of a round: row task (u, b, row) over every blocked row
+    // (padding rows carry identities through), column task (u, b, col) over
+    // every blocked column; u outermost, so a round of np < P planes runs the
+    // tasks with u < np.  Packed as u | b << 2 | idx << 8; -1 = no task.
+    constexpr int rt1 = C::ROWS * C::NBX, ct1 = C::TXM * C::NBY;
+    int rp[C::RT], cp[C::CT];
+#pragma unroll
+    for (int i = 0; i < C::RT; ++i) {
+        const int task = tid + i * NT;
+        const int u = task / rt1, rem = task % rt1;
+        rp[i] = task < P * rt1 ? (u | ((rem / C::ROWS) << 2) | ((rem % C::ROWS) << 8)) : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < C::CT; ++i) {
+        const int task = tid + i * NT;
+        const int u = task / ct1, rem = task % ct1;
+        cp[i] = task < P * ct1 ? (u | ((rem / C::TXM) << 2) | ((rem % C::TXM) << 8)) : -1;
+    }
+
+    const T* __restrict__ X = (const T*)a.X;
+    const int t_begin = qa * k0;
+    int t_end = (qb + 1) * k0;  // one block past the run: the suffix/inclusion lag
+    if (t_end > n0) t_end = n0;
+
+    const bool do_ex = a.exc != nullptr, do_inc = a.inc != nullptr;
+    T* __restrict__ exc = (T*)a.exc;
+    T* __restrict__ inc = (T*)a.inc;
+
+    Axis0State<T, Op, K0B> st;
+    st.P = e;
+    if (do_ex) {
+        st.P = bload<T>(buf((const T*)a.PX + (i64)qa * M, plane_bytes), mb);
+        if (a.Trest) st.P = Op::apply(st.P, bload<T>(buf(a.Trest, plane_bytes), mb));
+    }
+    // SX of the block being filled: loaded when the block starts, from an
+    // in-range block index; the identity past the last block is applied at use
+    T sx_raw = e;
+    bool sx_valid = false;
+
+    // Emit block (q-1) from the ring holding block q, then absorb block q.
+    // Ring slots past k0, and past the end of the tensor, hold the identity;
+    // rows of block q-1 past the tensor end fall outside the store range.
+    auto block_step = [&](int q) __attribute__((always_inline)) {
+        __syncthreads();
+        T v[K0B];
+#pragma unroll
+        for (int r = 0; r < K0B; ++r) v[r] = ring[r * NT + tid];
+        if (q != qa) {
+            const int xb = (q - 1) * k0;
+            const int nrows = n0 - xb < k0 ? n0 - xb : k0;
+            const unsigned blk_bytes = (unsigned)nrows * plane_bytes;
+            if (do_ex) {
+                const __amdgpu_buffer_rsrc_t ob = buf(exc + (i64)xb * M, blk_bytes);
+                T S = sx_valid ? sx_raw : e;
+#pragma unroll
+                for (int r = K0B - 1; r >= 0; --r) {
+                    S = Op::apply(v[r], S);
+                    bstore<T>(ob, mb + (unsigned)r * plane_bytes, Op::apply(st.pex[r], S));
+                }
+            }
+            if (do_inc) {
+                const __amdgpu_buffer_rsrc_t ob = buf(inc + (i64)xb * M, blk_bytes);
+                T p = e;
+#pragma unroll
+                for (int r = 0; r < K0B; ++r) {
+                    T val = st.rs[r];
+                    if (r > 0) { p = Op::apply(p, v[r - 1]); val = Op::apply(val, p); }
+                    bstore<T>(ob, mb + (unsigned)r * plane_bytes, val);
+                }
+            }
+        }
+        if (q < qb) st.absorb_all(v);
+    };
+    auto ring_fill_identity = [&](int from) {
+        for (int r = from; r < K0B; ++r) ring[r * NT + tid] = e;
+    };
+
+    // raw prefetched halo values (consumed only when staged into LDS)
+    T pre[P][C::NLOAD];
+    auto fetch_round = [&](int t, int np) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            const __amdgpu_buffer_rsrc_t pl = buf(X + (i64)(u < np ? t + u : t) * M, plane_bytes);
+#pragma unroll
+            for (int j = 0; j < C::NLOAD; ++j) pre[u][j] = bload<T>(pl, goff[j]);
+        }
+    };
+    auto round_len = [&](int tt, int rr) -> int {
+        int n = k0 - rr;
+        if (tt + n > t_end) n = t_end - tt;
+        return n < P ? n : P;
+    };
+
+    // rounds of up to P planes that stay inside one k0-block
+    int qlast = qa - 1;
+    int t = t_begin, q = qa, r0 = 0;
+    int np = t < t_end ? round_len(t, 0) : 0;
+    if (np > 0) fetch_round(t, np);
+    __syncthreads();  // identity fill visible before the first staging
+    while (t < t_end) {
+        if (r0 == 0) {
+            sx_valid = q < Qn;
+            if (do_ex)
+                sx_raw = bload<T>(buf((const T*)a.SX + (i64)(q < Qn ? q : Qn - 1) * M, plane_bytes),
+                                  mb);
+        }
+        // 1. stage this round's halo tiles; start loading the next round
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            if (u < np) {
+#pragma unroll
+                for (int j = 0; j < C::NLOAD; ++j) {
+                    const int o = loff[j] == P * SA ? P * SA : u * SA + loff[j];
+                    sA[o] = pre[u][j];
+                }
+            }
+        }
+        const int tn = t + np;
+        const int rn = r0 + np == k0 ? 0 : r0 + np;
+        const int npn = tn < t_end ? round_len(tn, rn) : 0;
+        if (npn > 0) fetch_round(tn, npn);
+        __syncthreads();
+        // 2. BDBS along x for every blocked halo row of every plane of the round
+#pragma unroll
+        for (int i = 0; i < C::RT; ++i) {
+            const int pk = rp[i];
+            if (pk >= 0 && (pk & 3) < np) {
+                const int u = pk & 3, b = (pk >> 2) & 63, row = pk >> 8;
+                bdbs_block<T, Op, KP, 1, 1>(sA + u * SA + row * C::PA + b * KP,
+                                            sB + u * SB + row * C::PB + b * KP);
+            }
+        }
+        __syncthreads();
+        // 3. BDBS along y for every blocked column into the ring slots
+#pragma unroll
+        for (int i = 0; i < C::CT; ++i) {
+            const int pk = cp[i];
+            if (pk >= 0 && (pk & 3) < np) {
+                const int u = pk & 3, b = (pk >> 2) & 63, col = pk >> 8;
+                bdbs_block<T, Op, KP, C::PB, C::TXM>(sB + u * SB + b * KP * C::PB + col,
+                                                      ring + (r0 + u) * NT + b * KP * C::TXM + col);
+            }
+        }
+        // 4. a block of W planes is complete: emit the previous block
+        if (r0 + np == k0 || tn == n0) {
+            if (r0 + np < k0) ring_fill_identity(r0 + np);  // the tensor ends inside the block
+            block_step(q);
+            qlast = q;
+        }
+        t = tn;
+        if (rn == 0) ++q;
+        r0 = rn;
+        np = npn;
+    }
+    // the block after the run lies past the tensor: emit the last block
+    if (qlast < qb) {
+        sx_valid = false;
+        ring_fill_identity(0);
+        block_step(qb);
+    }
+}
+
+template <typename T, class Op, int K0B, int KP>
+void launch_plane_kernel(PlaneArgs pa, hipStream_t st) {
+    using C = PlaneCfg<KP>;
+    const i64 ty = (i64)C::NBY * pa.ky, tx = (i64)C::NBX * pa.kx;
+    pa.tilesY = (pa.NY + ty - 1) / ty;
+    pa.tilesX = (pa.NX + tx - 1) / tx;
+    const i64 tiles = pa.tilesY * pa.tilesX * pa.MID;
+    // enough workgroups to cover every CU; each run of blocks reads one extra
+    // block of planes
+    i64 nseg = (256 + tiles - 1) / tiles;
+    if (nseg > pa.Q) nseg = pa.Q;
+    if (nseg < 1) nseg = 1;
+    pa.segblocks = (pa.Q + nseg - 1) / nseg;
+    pa.nseg = (pa.Q + pa.segblocks - 1) / pa.segblocks;
+    const i64 grid = tiles * pa.nseg;
+    hipLaunchKernelGGL((k_plane_axis0<T, Op, K0B, KP>), dim3((unsigned)grid), dim3(C::NT), 0, st,
+                       pa);
+}
+
+template <typename T, class Op, int K0B>
+void launch_plane_kp(PlaneArgs pa, hipStream_t st) {
+    const int km = pa.ky > pa.kx ? pa.ky : pa.kx;
+    if (km <= 2) launch_plane_kernel<T, Op, K0B, 2>(pa, st);
+    else if (km <= 4) launch_plane_kernel<T, Op, K0B, 4>(pa, st);
+    else if (km <= 8) launch_plane_kernel<T, Op, K0B, 8>(pa, st);
+    else launch_plane_kernel<T, Op, K0B, 16>(pa, st);
+}
+
+template <typename T, class Op>
+void launch_plane_axis0(const T* X, const T* PX, const T* SX, const T* Trest, T* exc, T* inc,
+                        i64 n0, i64 MID, i64 NY, i64 NX, i64 k0, i64 ky, i64 kx, i64 Q,
+                        hipStream_t st) {
+    KTimer timer("k_plane_axis0", st);
+    PlaneArgs pa{};
+    pa.X = X; pa.PX = PX; pa.SX = SX; pa.Trest = Trest; pa.exc = exc; pa.inc = inc;
+    pa.n0 = n0; pa.MID = MID; pa.NY = NY; pa.NX = NX; pa.M = MID * NY * NX; pa.Q = Q;
+    pa.k0 = (int)k0; pa.ky = (int)ky; pa.kx = (int)kx;
+    if (k0 <= 4) launch_plane_kp<T, Op, 4>(pa, st);
+    else if (k0 <= 8) launch_plane_kp<T, Op, 8>(pa, st);
+    else launch_plane_kp<T, Op, 16>(pa, st);
+}
+
+}  // namespace exs

@@ -1,0 +1,26 @@
+// exsum_plane_f32.hip -- fused plane kernel instantiated for float, and the
+// planner's eligibility test for it.
+#include "exsum_plane.hpp"
+
+namespace exs {
+
+bool plane_eligible(int d, const i64* n, const i64* k, int es) {
+    if (d < 3 || es != 4) return false;
+    if (k[0] > 16 || k[d - 2] > 16 || k[d - 1] > 16) return false;
+    // plane and block indices are 32-bit inside the kernel
+    if (n[0] + 64 >= ((i64)1 << 31)) return false;
+    if (n[d - 2] * n[d - 1] >= ((i64)1 << 31)) return false;
+    // byte offsets within two blocks of planes are 32-bit
+    i64 M = 1;
+    for (int i = 1; i < d; ++i) M *= n[i];
+    if (M * es * 32 >= ((i64)1 << 32)) return false;
+    return true;
+}
+
+template void launch_plane_axis0<float, OpSum>(const float*, const float*, const float*,
+                                               const float*, float*, float*, i64, i64, i64, i64,
+                                               i64, i64, i64, i64, hipStream_t);
+template void launch_plane_axis0<float, OpMax>(const float*, const float*, const float*,
+                                               const float*, float*, float*, i64, i64, i64, i64,
+                                               i64, i64, i64, i64, hipStream_t);
+}  // namespace exs

@@ -54,6 +54,14 @@ PLANE_CASES = [
     ((7, 45, 70), (2, 32, 32)),
     ((5, 6, 7, 40, 50), (2, 3, 4, 5, 6)),
     ((16, 8, 64, 64), (8, 8, 4, 4)),
+    # every (k0 bucket, plane-box bucket) pair, odd boxes, ragged tile edges
+    ((37, 50, 41), (3, 2, 1)),
+    ((29, 45, 70), (3, 3, 4)),
+    ((40, 33, 35), (5, 7, 6)),
+    ((41, 70, 39), (7, 11, 13)),
+    ((50, 20, 100), (12, 2, 16)),
+    ((33, 64, 31), (16, 5, 3)),
+    ((65, 47, 48), (13, 16, 9)),
 ]
 
 
