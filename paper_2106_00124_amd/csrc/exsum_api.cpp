@@ -167,6 +167,12 @@ static const T* filter_axes(const T* src, const i64* n, const i64* k, int d, int
     return cur;
 }
 
+// The LDS-tiled 2-D BDBS kernel is built for 4-byte element types only.
+template <typename T, class Op>
+static void plane2_call(const T* X, T* W, i64 O, i64 NY, i64 NX, i64 ky, i64 kx, hipStream_t st) {
+    if constexpr (sizeof(T) == 4) launch_plane_bdbs<T, Op>(X, W, O, NY, NX, ky, kx, st);
+}
+
 // The fused plane kernel is built for 4-byte element types only.
 template <typename T, class Op>
 static void plane_call(const T* X, const T* PX, const T* SX, const T* Trest, T* exc, T* inc,
@@ -256,7 +262,20 @@ static exs_status run_generic(const exs_job* job, Arena& ar, hipStream_t st) {
         gn[0] = Q[j];
         gk[0] = 1;
         for (int a = 1; a < dj; ++a) { gn[a] = n[j + a]; gk[a] = k[j + a]; }
-        const T* Gw = filter_axes<T, Op>(Ga, gn, gk, dj, 1, dj - 1, gb0, gb1, dry, st);
+        const T* Gw;
+        if (j == 0 && fused && plane2_eligible(n[d - 2], n[d - 1], k[d - 2], k[d - 1],
+                                               (int)sizeof(T))) {
+            // middle axes by the generic passes, the two trailing axes in one
+            // LDS-tiled pass
+            const T* G1 = filter_axes<T, Op>(Ga, gn, gk, dj, 1, dj - 3, gb0, gb1, dry, st);
+            T* G2 = G1 == gb0 ? gb1 : gb0;
+            if (!dry)
+                plane2_call<T, Op>(G1, G2, Q[0] * prod(n, 1, d - 2), n[d - 2], n[d - 1], k[d - 2],
+                                   k[d - 1], st);
+            Gw = G2;
+        } else {
+            Gw = filter_axes<T, Op>(Ga, gn, gk, dj, 1, dj - 1, gb0, gb1, dry, st);
+        }
         if (!dry) launch_blockscan<T, Op>(Gw, Ga, PX[j], SX[j], R[j + 1], Q[j], M[j], st);
     }
     // bottom-up: stream the first axis of each level, adding the level below

@@ -29,6 +29,9 @@ void launch_plane_axis0(const T* X, const T* PX, const T* SX, const T* Trest, T*
                         i64 n0, i64 MID, i64 NY, i64 NX, i64 k0, i64 ky, i64 kx, i64 Q,
                         hipStream_t st);
 bool plane_eligible(int d, const i64* n, const i64* k, int es);
+template <typename T, class Op>
+void launch_plane_bdbs(const T* X, T* W, i64 O, i64 NY, i64 NX, i64 ky, i64 kx, hipStream_t st);
+bool plane2_eligible(i64 NY, i64 NX, i64 ky, i64 kx, int es);
 void launch_fill(void* out, i64 count, int dtype, int kind, uint64_t seed, i64 lo, i64 hi,
                  float scale, hipStream_t st);
 

@@ -88,8 +88,55 @@ __global__ __launch_bounds__(256) void k_blockagg(const T* __restrict__ X, T* __
     const i64 t0 = q * k0;
     const i64 t1 = t0 + k0 < n0 ? t0 + k0 : n0;
     T s = Op::template id<T>();
+#pragma unroll 8
     for (i64 t = t0; t < t1; ++t) s = Op::apply(s, X[t * M + m]);
     Ga[idx] = s;
+}
+
+// The same for 4-byte elements with M % 4 == 0: each thread owns 4
+// consecutive points (16-byte loads), 8 planes in flight at a time.
+template <typename T, class Op>
+__global__ __launch_bounds__(256) void k_blockagg4(const T* __restrict__ X, T* __restrict__ Ga,
+                                                   i64 n0, i64 M, i64 k0, i64 Q) {
+    static_assert(sizeof(T) == 4, "4-byte elements");
+    const i64 M4 = M >> 2;
+    const i64 idx = gtid();
+    if (idx >= Q * M4) return;
+    // blocks in descending order: the planes read last (low axis-0 index) are
+    // the ones the streaming kernel reads first, while they may still sit in
+    // the last-level cache
+    const i64 m4 = idx % M4, q = Q - 1 - idx / M4;
+    const i64 t0 = q * k0;
+    const i64 t1 = t0 + k0 < n0 ? t0 + k0 : n0;
+    const uint4* __restrict__ src = (const uint4*)X + m4;
+    const T e = Op::template id<T>();
+    T s0 = e, s1 = e, s2 = e, s3 = e;
+    i64 t = t0;
+    for (; t + 8 <= t1; t += 8) {
+        uint4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = src[(t + u) * M4];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            s0 = Op::apply(s0, __builtin_bit_cast(T, v[u].x));
+            s1 = Op::apply(s1, __builtin_bit_cast(T, v[u].y));
+            s2 = Op::apply(s2, __builtin_bit_cast(T, v[u].z));
+            s3 = Op::apply(s3, __builtin_bit_cast(T, v[u].w));
+        }
+    }
+    for (; t < t1; ++t) {
+        const uint4 v = src[t * M4];
+        s0 = Op::apply(s0, __builtin_bit_cast(T, v.x));
+        s1 = Op::apply(s1, __builtin_bit_cast(T, v.y));
+        s2 = Op::apply(s2, __builtin_bit_cast(T, v.z));
+        s3 = Op::apply(s3, __builtin_bit_cast(T, v.w));
+    }
+    uint4 o;
+    o.x = __builtin_bit_cast(unsigned, s0);
+    o.y = __builtin_bit_cast(unsigned, s1);
+    o.z = __builtin_bit_cast(unsigned, s2);
+    o.w = __builtin_bit_cast(unsigned, s3);
+    ((uint4*)Ga)[q * M4 + m4] = o;
 }
 
 // Per point m: PX[q] = op of Gw[q'] for q' < q, SX[q] = op of Gw[q'] for
@@ -103,12 +150,14 @@ __global__ __launch_bounds__(256) void k_blockscan(const T* __restrict__ Gw,
     if (m >= M) return;
     const T e = Op::template id<T>();
     T p = e, r = e;
+#pragma unroll 8
     for (i64 q = 0; q < Q; ++q) {
         PX[q * M + m] = p;
         p = Op::apply(p, Gw[q * M + m]);
         r = Op::apply(r, Ga[q * M + m]);
     }
     T s = e;
+#pragma unroll 8
     for (i64 q = Q - 1; q >= 0; --q) {
         SX[q * M + m] = s;
         s = Op::apply(Gw[q * M + m], s);
@@ -292,6 +341,13 @@ void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st
 template <typename T, class Op>
 void launch_blockagg(const T* X, T* Ga, i64 n0, i64 M, i64 k0, i64 Q, hipStream_t st) {
     KTimer timer("k_blockagg", st);
+    if constexpr (sizeof(T) == 4) {
+        if (M % 4 == 0 && ((uintptr_t)X & 15) == 0 && ((uintptr_t)Ga & 15) == 0) {
+            hipLaunchKernelGGL((k_blockagg4<T, Op>), dim3(grid_for(Q * (M / 4))), dim3(256), 0, st,
+                               X, Ga, n0, M, k0, Q);
+            return;
+        }
+    }
     hipLaunchKernelGGL((k_blockagg<T, Op>), dim3(grid_for(Q * M)), dim3(256), 0, st, X, Ga, n0,
                        M, k0, Q);
 }

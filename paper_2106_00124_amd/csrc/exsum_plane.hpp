@@ -332,6 +332,154 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// 2-D BDBS of every plane of a (O, NY, NX) tensor over its two trailing axes
+// (BDBS-Along-Dim along y and x, Sec. 5), with the same blocked LDS tiles as
+// the streaming kernel: P planes per round, results staged through LDS so
+// each thread stores its own point (coalesced rows).
+// ---------------------------------------------------------------------------
+struct Plane2Args {
+    const void* X;
+    void* W;
+    i64 O, NY, NX;
+    int ky, kx;
+    i64 tilesY, tilesX;
+};
+
+template <typename T, class Op, int KP>
+__global__ void __launch_bounds__(1024) k_plane_bdbs(Plane2Args a) {
+    using C = PlaneCfg<KP>;
+    constexpr int NT = C::NT, P = C::P, SA = C::SA, SB = C::SB;
+    __shared__ T sA[P * SA + 1];
+    __shared__ T sB[P * SB];
+    __shared__ T sW[P * NT];
+
+    const T e = Op::template id<T>();
+    const int tid = threadIdx.x;
+    i64 wg = blockIdx.x;
+    const i64 nwg = (i64)gridDim.x;
+    if ((nwg & 7) == 0) wg = (wg & 7) * (nwg >> 3) + (wg >> 3);
+    const i64 tiles = a.tilesY * a.tilesX;
+    const i64 tile = wg % tiles;
+    const int grp = (int)(wg / tiles);  // which group of planes
+    const int ky = a.ky, kx = a.kx;
+    const int NY = (int)a.NY, NX = (int)a.NX;
+    const int y0 = (int)(tile / a.tilesX) * (C::NBY * ky);
+    const int x0 = (int)(tile % a.tilesX) * (C::NBX * kx);
+    const unsigned plane_bytes = (unsigned)((i64)NY * NX * (i64)sizeof(T));
+
+    const int pyb = tid / C::TXM, pxb = tid % C::TXM;
+    const int py = (pyb / KP) * ky + pyb % KP, px = (pxb / KP) * kx + pxb % KP;
+    const bool pvalid = pyb % KP < ky && pxb % KP < kx && y0 + py < NY && x0 + px < NX;
+    const unsigned mb = pvalid ? (unsigned)((y0 + py) * NX + x0 + px) * sizeof(T) : plane_bytes;
+
+    for (int i = tid; i < P * SA; i += NT) sA[i] = e;
+    const int rows_in = C::NBY * ky + ky - 1, cols_in = C::NBX * kx + kx - 1;
+    const int count = rows_in * cols_in;
+    int loff[C::NLOAD];
+    unsigned goff[C::NLOAD];
+#pragma unroll
+    for (int j = 0; j < C::NLOAD; ++j) {
+        const int el = tid + j * NT;
+        const int r = el / cols_in, c = el % cols_in;
+        const bool inside = el < count && y0 + r < NY && x0 + c < NX;
+        loff[j] = inside ? ((r / ky) * KP + r % ky) * C::PA + (c / kx) * KP + c % kx : P * SA;
+        goff[j] = inside ? (unsigned)((y0 + r) * NX + x0 + c) * sizeof(T) : 0u;
+    }
+    constexpr int rt1 = C::ROWS * C::NBX, ct1 = C::TXM * C::NBY;
+    int rp[C::RT], cp[C::CT];
+#pragma unroll
+    for (int i = 0; i < C::RT; ++i) {
+        const int task = tid + i * NT;
+        const int u = task / rt1, rem = task % rt1;
+        rp[i] = task < P * rt1 ? (u | ((rem / C::ROWS) << 2) | ((rem % C::ROWS) << 8)) : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < C::CT; ++i) {
+        const int task = tid + i * NT;
+        const int u = task / ct1, rem = task % ct1;
+        cp[i] = task < P * ct1 ? (u | ((rem / C::TXM) << 2) | ((rem % C::TXM) << 8)) : -1;
+    }
+    const T* __restrict__ X = (const T*)a.X;
+    T* __restrict__ W = (T*)a.W;
+    const i64 plane = (i64)NY * NX;
+    __syncthreads();
+    // each workgroup walks planes grp, grp + G, ... in rounds of P
+    const i64 G = (i64)gridDim.x / tiles;
+    for (i64 o0 = (i64)grp * P; o0 < a.O; o0 += G * P) {
+        const int np = a.O - o0 < P ? (int)(a.O - o0) : P;
+        T v[P][C::NLOAD];
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            const __amdgpu_buffer_rsrc_t pl = buf(X + (o0 + (u < np ? u : 0)) * plane, plane_bytes);
+#pragma unroll
+            for (int j = 0; j < C::NLOAD; ++j) v[u][j] = bload<T>(pl, goff[j]);
+        }
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            if (u < np) {
+#pragma unroll
+                for (int j = 0; j < C::NLOAD; ++j) {
+                    const int o = loff[j] == P * SA ? P * SA : u * SA + loff[j];
+                    sA[o] = v[u][j];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < C::RT; ++i) {
+            const int pk = rp[i];
+            if (pk >= 0 && (pk & 3) < np) {
+                const int u = pk & 3, b = (pk >> 2) & 63, row = pk >> 8;
+                bdbs_block<T, Op, KP, 1, 1>(sA + u * SA + row * C::PA + b * KP,
+                                            sB + u * SB + row * C::PB + b * KP);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < C::CT; ++i) {
+            const int pk = cp[i];
+            if (pk >= 0 && (pk & 3) < np) {
+                const int u = pk & 3, b = (pk >> 2) & 63, col = pk >> 8;
+                bdbs_block<T, Op, KP, C::PB, C::TXM>(sB + u * SB + b * KP * C::PB + col,
+                                                      sW + u * NT + b * KP * C::TXM + col);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < P; ++u)
+            if (u < np) bstore<T>(buf(W + (o0 + u) * plane, plane_bytes), mb, sW[u * NT + tid]);
+    }
+}
+
+template <typename T, class Op, int KP>
+void launch_plane_bdbs_kp(Plane2Args pa, hipStream_t st) {
+    using C = PlaneCfg<KP>;
+    const i64 ty = (i64)C::NBY * pa.ky, tx = (i64)C::NBX * pa.kx;
+    pa.tilesY = (pa.NY + ty - 1) / ty;
+    pa.tilesX = (pa.NX + tx - 1) / tx;
+    const i64 tiles = pa.tilesY * pa.tilesX;
+    // plane groups so that the grid covers the CUs (each group: P planes per round)
+    i64 groups = (512 + tiles - 1) / tiles;
+    const i64 maxg = (pa.O + C::P - 1) / C::P;
+    if (groups > maxg) groups = maxg;
+    if (groups < 1) groups = 1;
+    hipLaunchKernelGGL((k_plane_bdbs<T, Op, KP>), dim3((unsigned)(tiles * groups)), dim3(C::NT),
+                       0, st, pa);
+}
+
+template <typename T, class Op>
+void launch_plane_bdbs(const T* X, T* W, i64 O, i64 NY, i64 NX, i64 ky, i64 kx, hipStream_t st) {
+    KTimer timer("k_plane_bdbs", st);
+    Plane2Args pa{};
+    pa.X = X; pa.W = W; pa.O = O; pa.NY = NY; pa.NX = NX; pa.ky = (int)ky; pa.kx = (int)kx;
+    const i64 km = ky > kx ? ky : kx;
+    if (km <= 2) launch_plane_bdbs_kp<T, Op, 2>(pa, st);
+    else if (km <= 4) launch_plane_bdbs_kp<T, Op, 4>(pa, st);
+    else if (km <= 8) launch_plane_bdbs_kp<T, Op, 8>(pa, st);
+    else launch_plane_bdbs_kp<T, Op, 16>(pa, st);
+}
+
 template <typename T, class Op, int K0B, int KP>
 void launch_plane_kernel(PlaneArgs pa, hipStream_t st) {
     using C = PlaneCfg<KP>;

@@ -17,10 +17,18 @@ bool plane_eligible(int d, const i64* n, const i64* k, int es) {
     return true;
 }
 
+bool plane2_eligible(i64 NY, i64 NX, i64 ky, i64 kx, int es) {
+    return es == 4 && ky <= 16 && kx <= 16 && NY * NX * es < ((i64)1 << 31);
+}
+
 template void launch_plane_axis0<float, OpSum>(const float*, const float*, const float*,
                                                const float*, float*, float*, i64, i64, i64, i64,
                                                i64, i64, i64, i64, hipStream_t);
 template void launch_plane_axis0<float, OpMax>(const float*, const float*, const float*,
                                                const float*, float*, float*, i64, i64, i64, i64,
                                                i64, i64, i64, i64, hipStream_t);
+template void launch_plane_bdbs<float, OpSum>(const float*, float*, i64, i64, i64, i64, i64,
+                                             hipStream_t);
+template void launch_plane_bdbs<float, OpMax>(const float*, float*, i64, i64, i64, i64, i64,
+                                             hipStream_t);
 }  // namespace exs
