@@ -108,3 +108,63 @@ def fill(out, kind, seed, lo=-100, hi=100, stream=None):
 
 def version() -> str:
     return _lib.lib().exs_version().decode()
+
+
+class Batch:
+    """Batched form: many jobs, one hipGraph launch (see exs_batch_* in exsum.h).
+
+    ``items`` is a list of ``(x, box, op, mode)`` with ``x`` a contiguous
+    device tensor.  Outputs are allocated here and exposed as ``outputs``
+    (list of ``(inc, exc)``); they and the inputs must stay alive while the
+    batch is used.  ``tune_cache`` is a JSON path for the autotuner (None:
+    built-in settings).
+    """
+
+    def __init__(self, items, tune_cache=None):
+        import torch
+        self._keep = []
+        self.outputs = []
+        jobs = (_lib.ExsJob * len(items))()
+        for i, (x, box, op, mode) in enumerate(items):
+            if not x.is_cuda or not x.is_contiguous():
+                raise ExsError(1, "batch inputs must be contiguous device tensors")
+            m = _mode_code(mode)
+            inc = torch.empty_like(x) if m & _lib.INCLUDED else None
+            exc = torch.empty_like(x) if m & _lib.EXCLUDED else None
+            jobs[i] = job_for(x, box, op, m, inc, exc)
+            self._keep.append(x)
+            self.outputs.append((inc, exc))
+        h = ctypes.c_void_p()
+        cache = tune_cache.encode() if tune_cache else None
+        _lib.check(_lib.lib().exs_batch_create(jobs, len(items), cache, ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_size_t()
+        _lib.check(_lib.lib().exs_batch_workspace_size(h, ctypes.byref(n)))
+        self.workspace = torch.empty(max(n.value, 1), dtype=torch.uint8,
+                                     device=items[0][0].device)
+
+    def launch(self, stream=None):
+        _lib.check(_lib.lib().exs_batch_launch(self._h, ctypes.c_void_p(self.workspace.data_ptr()),
+                                               self.workspace.numel(), _stream_ptr(stream)))
+
+    def launch_eager(self, stream=None):
+        _lib.check(_lib.lib().exs_batch_launch_eager(
+            self._h, ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+            _stream_ptr(stream)))
+
+    def info(self):
+        nodes = ctypes.c_int32()
+        items = ctypes.c_int64()
+        _lib.check(_lib.lib().exs_batch_info(self._h, ctypes.byref(nodes), ctypes.byref(items)))
+        return {"graph_nodes": nodes.value, "work_items": items.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().exs_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

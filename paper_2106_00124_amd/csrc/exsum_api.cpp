@@ -28,6 +28,7 @@
 #include <vector>
 
 #include "exsum_internal.hpp"
+#include "exsum_plan.hpp"
 
 namespace exs {
 
@@ -128,183 +129,45 @@ KTimer::~KTimer() {
     if (slot < (int)g_pending.size()) hipEventRecord(g_pending[slot].b, st);
 }
 
-// Bump allocator over the caller's workspace.  In "dry" mode it only
-// measures, so sizing and execution share one code path.
-struct Arena {
-    char* base = nullptr;
-    size_t cap = 0, off = 0;
-    bool dry = true;
-    template <typename T>
-    T* take(i64 count) {
-        off = (off + 255) & ~(size_t)255;
-        T* p = dry ? nullptr : (T*)(base + off);
-        off += (size_t)count * sizeof(T);
-        return p;
+// Launches every step at once on one stream (the plain call).
+template <typename T, class Op>
+struct EagerSink {
+    hipStream_t st;
+    bool fused_ok = true;
+    void level(int j) { set_timing_tag(j); }
+    void bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k) {
+        launch_bdbs<T, Op>(in, out, O, n, I, k, st);
+    }
+    void blockagg(const T* X, T* Ga, i64 n0, i64 M, i64 k0, i64 Q) {
+        launch_blockagg<T, Op>(X, Ga, n0, M, k0, Q, st);
+    }
+    void blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M) {
+        launch_blockscan<T, Op>(Gw, Ga, PX, SX, R, Q, M, st);
+    }
+    void axis0(const T* W, const T* PX, const T* SX, const T* Trest, T* exc, T* inc, i64 n0,
+               i64 M, i64 k0, i64 Q) {
+        launch_axis0<T, Op>(W, PX, SX, Trest, exc, inc, n0, M, k0, Q, st);
+    }
+    // the fused kernels are built for 4-byte element types only
+    void plane_axis0(const T* X, const T* PX, const T* SX, const T* Trest, T* exc, T* inc, i64 n0,
+                     i64 MID, i64 NY, i64 NX, i64 k0, i64 ky, i64 kx, i64 Q) {
+        if constexpr (sizeof(T) == 4)
+            launch_plane_axis0<T, Op>(X, PX, SX, Trest, exc, inc, n0, MID, NY, NX, k0, ky, kx, Q,
+                                      st);
+    }
+    void plane_bdbs(const T* X, T* W, i64 O, i64 NY, i64 NX, i64 ky, i64 kx) {
+        if constexpr (sizeof(T) == 4) launch_plane_bdbs<T, Op>(X, W, O, NY, NX, ky, kx, st);
     }
 };
 
-static i64 prod(const i64* v, int a, int b) {
-    i64 p = 1;
-    for (int i = a; i < b; ++i) p *= v[i];
-    return p;
-}
-
-// Box-sum a rank-d tensor over axes last .. first (last axis first: the
-// innermost reduction of the nested definition in Sec. 2), ping-ponging
-// between wb[0] and wb[1].  Returns the result (src itself if no axis).
-template <typename T, class Op>
-static const T* filter_axes(const T* src, const i64* n, const i64* k, int d, int first, int last,
-                            T* wb0, T* wb1, bool dry, hipStream_t st) {
-    const T* cur = src;
-    T* wb[2] = {wb0, wb1};
-    int which = 0;
-    for (int a = last; a >= first; --a) {
-        T* dst = wb[which];
-        which ^= 1;
-        if (!dry) launch_bdbs<T, Op>(cur, dst, prod(n, 0, a), n[a], prod(n, a + 1, d), k[a], st);
-        cur = dst;
-    }
-    return cur;
-}
-
-// The LDS-tiled 2-D BDBS kernel is built for 4-byte element types only.
-template <typename T, class Op>
-static void plane2_call(const T* X, T* W, i64 O, i64 NY, i64 NX, i64 ky, i64 kx, hipStream_t st) {
-    if constexpr (sizeof(T) == 4) launch_plane_bdbs<T, Op>(X, W, O, NY, NX, ky, kx, st);
-}
-
-// The fused plane kernel is built for 4-byte element types only.
-template <typename T, class Op>
-static void plane_call(const T* X, const T* PX, const T* SX, const T* Trest, T* exc, T* inc,
-                       i64 n0, i64 MID, i64 NY, i64 NX, i64 k0, i64 ky, i64 kx, i64 Q,
-                       hipStream_t st) {
-    if constexpr (sizeof(T) == 4)
-        launch_plane_axis0<T, Op>(X, PX, SX, Trest, exc, inc, n0, MID, NY, NX, k0, ky, kx, Q, st);
-}
-
-template <typename T, class Op>
-static exs_status run_generic(const exs_job* job, Arena& ar, hipStream_t st) {
-    const int d = job->d;
-    i64 n[EXS_MAX_RANK], k[EXS_MAX_RANK];
-    for (int i = 0; i < d; ++i) { n[i] = job->dims[i]; k[i] = job->box[i]; }
-    const T* A = (const T*)job->in_dev;
-    T* inc = (job->mode & EXS_INCLUDED) ? (T*)job->inc_out_dev : nullptr;
-    T* exc = (job->mode & EXS_EXCLUDED) ? (T*)job->exc_out_dev : nullptr;
-    const bool want_exc = job->mode & EXS_EXCLUDED;
-    const bool dry = ar.dry;
-    const i64 N = prod(n, 0, d);
-    // level 0 streams axis 0 with the fused plane kernel when it applies; it
-    // box-sums the two trailing axes itself, the middle axes are done first
-    const bool fused = sizeof(T) == 4 && plane_eligible(d, n, k, (int)sizeof(T));
-
-    // buffers for box-summed tensors, shared by every level: level j needs
-    // (d_j - 1) passes over N_j elements, the fused level 0 only d - 3
-    int wb_count = 0;
-    i64 wb_elems = 0;
-    for (int j = 0; j < (want_exc ? d : 1); ++j) {
-        const int passes = (j == 0 && fused) ? std::max(0, d - 3) : d - j - 1;
-        if (passes > 0) {
-            wb_count = std::max(wb_count, std::min(2, passes));
-            wb_elems = std::max(wb_elems, prod(n, j, d));
-        }
-    }
-    T* wb0 = wb_count >= 1 ? ar.take<T>(wb_elems) : nullptr;
-    T* wb1 = wb_count >= 2 ? ar.take<T>(wb_elems) : nullptr;
-
-    set_timing_tag(0);
-    if (!want_exc) {
-        // included sums only: BDBS along every axis
-        if (fused) {
-            const T* X0 = filter_axes<T, Op>(A, n, k, d, 1, d - 3, wb0, wb1, dry, st);
-            if (!dry)
-                plane_call<T, Op>(X0, nullptr, nullptr, nullptr, nullptr, inc, n[0],
-                                          prod(n, 1, d - 2), n[d - 2], n[d - 1], k[0], k[d - 2],
-                                          k[d - 1], (n[0] + k[0] - 1) / k[0], st);
-            return EXS_OK;
-        }
-        const T* W = filter_axes<T, Op>(A, n, k, d, 1, d - 1, wb0, wb1, dry, st);
-        if (!dry) launch_bdbs<T, Op>(W, inc, 1, n[0], prod(n, 1, d), k[0], st);
-        return EXS_OK;
-    }
-
-    // per-level sizes
-    i64 Q[EXS_MAX_RANK], M[EXS_MAX_RANK];
-    i64 maxQM = 0;
-    for (int j = 0; j < d; ++j) {
-        Q[j] = (n[j] + k[j] - 1) / k[j];
-        M[j] = prod(n, j + 1, d);
-        maxQM = std::max(maxQM, Q[j] * M[j]);
-    }
-    T* Ga = ar.take<T>(maxQM);
-    const int ngb = std::min(2, d - 1);
-    T* gb0 = ngb >= 1 ? ar.take<T>(maxQM) : nullptr;
-    T* gb1 = ngb >= 2 ? ar.take<T>(maxQM) : nullptr;
-    T *PX[EXS_MAX_RANK], *SX[EXS_MAX_RANK], *R[EXS_MAX_RANK + 1];
-    R[0] = nullptr;
-    for (int j = 0; j < d; ++j) {
-        PX[j] = ar.take<T>(Q[j] * M[j]);
-        SX[j] = ar.take<T>(Q[j] * M[j]);
-        R[j + 1] = ar.take<T>(M[j]);
-    }
-    // lower-level excluded sums: level j >= 1 writes tb[j % 2] (N_j <= N_1)
-    T* tb0 = d >= 3 ? ar.take<T>(M[0]) : nullptr;
-    T* tb1 = d >= 2 ? ar.take<T>(M[0]) : nullptr;
-    T* tb[2] = {tb0, tb1};
-
-    // top-down: block aggregates, their box-sums over the other axes, block
-    // scans, and the reduction that feeds the next level
-    for (int j = 0; j < d; ++j) {
-        const int dj = d - j;
-        const T* src = j == 0 ? A : R[j];
-        set_timing_tag(j);
-        if (!dry) launch_blockagg<T, Op>(src, Ga, n[j], M[j], k[j], Q[j], st);
-        i64 gn[EXS_MAX_RANK], gk[EXS_MAX_RANK];
-        gn[0] = Q[j];
-        gk[0] = 1;
-        for (int a = 1; a < dj; ++a) { gn[a] = n[j + a]; gk[a] = k[j + a]; }
-        const T* Gw;
-        if (j == 0 && fused && plane2_eligible(n[d - 2], n[d - 1], k[d - 2], k[d - 1],
-                                               (int)sizeof(T))) {
-            // middle axes by the generic passes, the two trailing axes in one
-            // LDS-tiled pass
-            const T* G1 = filter_axes<T, Op>(Ga, gn, gk, dj, 1, dj - 3, gb0, gb1, dry, st);
-            T* G2 = G1 == gb0 ? gb1 : gb0;
-            if (!dry)
-                plane2_call<T, Op>(G1, G2, Q[0] * prod(n, 1, d - 2), n[d - 2], n[d - 1], k[d - 2],
-                                   k[d - 1], st);
-            Gw = G2;
-        } else {
-            Gw = filter_axes<T, Op>(Ga, gn, gk, dj, 1, dj - 1, gb0, gb1, dry, st);
-        }
-        if (!dry) launch_blockscan<T, Op>(Gw, Ga, PX[j], SX[j], R[j + 1], Q[j], M[j], st);
-    }
-    // bottom-up: stream the first axis of each level, adding the level below
-    for (int j = d - 1; j >= 0; --j) {
-        const int dj = d - j;
-        const T* src = j == 0 ? A : R[j];
-        set_timing_tag(j);
-        T* out = j == 0 ? exc : tb[j % 2];
-        const T* Trest = j == d - 1 ? nullptr : tb[(j + 1) % 2];
-        if (j == 0 && fused) {
-            const T* X0 = filter_axes<T, Op>(A, n, k, d, 1, d - 3, wb0, wb1, dry, st);
-            if (!dry)
-                plane_call<T, Op>(X0, PX[0], SX[0], Trest, exc, inc, n[0],
-                                          prod(n, 1, d - 2), n[d - 2], n[d - 1], k[0], k[d - 2],
-                                          k[d - 1], Q[0], st);
-            continue;
-        }
-        const T* W = filter_axes<T, Op>(src, n + j, k + j, dj, 1, dj - 1, wb0, wb1, dry, st);
-        if (!dry)
-            launch_axis0<T, Op>(W, PX[j], SX[j], Trest, out, j == 0 ? inc : nullptr, n[j], M[j],
-                                k[j], Q[j], st);
-    }
-    return EXS_OK;
-}
-
 template <typename T>
 static exs_status run_dtype(const exs_job* job, Arena& ar, hipStream_t st) {
-    if (job->op == EXS_SUM) return run_generic<T, OpSum>(job, ar, st);
-    return run_generic<T, OpMax>(job, ar, st);
+    if (job->op == EXS_SUM) {
+        EagerSink<T, OpSum> sink{st};
+        return plan_job<T>(job, ar, sink);
+    }
+    EagerSink<T, OpMax> sink{st};
+    return plan_job<T>(job, ar, sink);
 }
 
 static exs_status dispatch(const exs_job* job, Arena& ar, hipStream_t st) {

@@ -1,41 +1,541 @@
-// exsum_batch.cpp -- batched form (placeholder until the batched executor lands).
+// exsum_batch.cpp -- batched form: many tensors of uneven shapes, ranks,
+// boxes, dtypes and operators in one hipGraph launch of persistent work-list
+// kernels, with an autotuner for the work granularity.
+//
+// Paper: Xu, Fraser, Leiserson, "Multidimensional Included and Excluded Sums"
+// (SIAM ACDA 2021, arXiv 2106.00124).
+//
+// Each job is planned by the same planner as the plain call (exsum_plan.hpp),
+// but its steps are recorded instead of launched.  Step p of every job goes
+// to phase p (a job's recorded order respects its dependencies); within a
+// phase, steps of one kind, dtype, operator and register bucket share one
+// work-list launch (exsum_worklist.hip).  Every job gets its own region of
+// the batch workspace.  The whole sequence is captured once per workspace
+// into a hipGraph and replayed.
+//
+// Autotuning: the work granularity (minimum tasks per step, which sets how
+// many chunks a row or axis-0 stream is cut into) and the persistent grid
+// size (workgroups per CU) are chosen by timing candidate settings on the
+// batch itself; the winner is cached in a JSON file keyed by a signature of
+// the batch's shapes, boxes, dtypes, operators and modes.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <tuple>
+#include <string>
+#include <vector>
+
 #include "exsum_internal.hpp"
+#include "exsum_plan.hpp"
+#include "exsum_tasks.hpp"
+
+namespace exs {
+
+struct TuneCfg {
+    i64 min_tasks = 16384;  // minimum tasks per bdbs / axis-0 step
+    int wg_per_cu = 4;      // persistent workgroups per CU
+};
+
+struct Rec {
+    Step s;
+    int dtype, op, kb;
+};
+
+// Records the planner's steps (the generic kernels only).
+template <typename T, class Op>
+struct ListSink {
+    std::vector<Rec>* out;
+    int dtype, op;
+    TuneCfg cfg;
+    bool fused_ok = false;
+    void level(int) {}
+    void push(const Step& s, int kb) { out->push_back(Rec{s, dtype, op, kb}); }
+    void bdbs(const T* in, T* o, i64 O, i64 n, i64 I, i64 k) {
+        Step s{};
+        s.k = (int)k;
+        s.in0 = in;
+        s.out0 = o;
+        s.O = O;
+        s.n = n;
+        s.I = I;
+        const int kb = bucket_for(k);
+        if (kb == 0) {
+            s.kind = SK_BDBS2;
+            s.ntasks = O * I;
+            push(s, 1);
+            return;
+        }
+        s.kind = SK_BDBS;
+        const i64 nb = (n + k - 1) / k, cols = O * I;
+        i64 nch = (cfg.min_tasks + cols - 1) / cols;
+        if (nch > nb) nch = nb;
+        if (nch < 1) nch = 1;
+        s.cb = (nb + nch - 1) / nch;
+        s.nchunks = (nb + s.cb - 1) / s.cb;
+        s.ntasks = cols * s.nchunks;
+        push(s, kb);
+    }
+    void blockagg(const T* X, T* Ga, i64 n0, i64 M, i64 k0, i64 Q) {
+        Step s{};
+        s.kind = SK_AGG;
+        s.k = (int)k0;
+        s.in0 = X;
+        s.out0 = Ga;
+        s.n = n0;
+        s.I = M;
+        s.Q = Q;
+        s.ntasks = Q * M;
+        push(s, 1);
+    }
+    void blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M) {
+        Step s{};
+        s.kind = SK_SCAN;
+        s.in0 = Gw;
+        s.in1 = Ga;
+        s.out0 = PX;
+        s.out1 = SX;
+        s.out2 = R;
+        s.Q = Q;
+        s.I = M;
+        s.ntasks = M;
+        push(s, 1);
+    }
+    void axis0(const T* W, const T* PX, const T* SX, const T* Trest, T* exc, T* inc, i64 n0,
+               i64 M, i64 k0, i64 Q) {
+        const int kb = bucket_for(k0);
+        if (kb == 0) {
+            if (exc) {
+                Step s{};
+                s.kind = SK_EX2;
+                s.k = (int)k0;
+                s.in0 = W;
+                s.in3 = Trest;
+                s.out0 = exc;
+                s.n = n0;
+                s.I = M;
+                s.ntasks = M;
+                push(s, 1);
+            }
+            if (inc) bdbs(W, inc, 1, n0, M, k0);
+            return;
+        }
+        Step s{};
+        s.kind = SK_AX0;
+        s.k = (int)k0;
+        s.in0 = W;
+        s.in1 = PX;
+        s.in2 = SX;
+        s.in3 = Trest;
+        s.out0 = exc;
+        s.out1 = inc;
+        s.n = n0;
+        s.I = M;
+        s.Q = Q;
+        i64 nseg = (cfg.min_tasks + M - 1) / M;
+        if (nseg > Q) nseg = Q;
+        if (nseg < 1) nseg = 1;
+        s.cb = (Q + nseg - 1) / nseg;
+        s.nchunks = (Q + s.cb - 1) / s.cb;
+        s.ntasks = M * s.nchunks;
+        push(s, kb);
+    }
+    void plane_axis0(const T*, const T*, const T*, const T*, T*, T*, i64, i64, i64, i64, i64, i64,
+                     i64, i64) {}
+    void plane_bdbs(const T*, T*, i64, i64, i64, i64, i64) {}
+};
+
+template <typename T, class Op>
+static exs_status plan_into(const exs_job* job, Arena& ar, std::vector<Rec>* out,
+                            const TuneCfg& cfg) {
+    ListSink<T, Op> sink{out, job->dtype, job->op, cfg};
+    return plan_job<T>(job, ar, sink);
+}
+
+static exs_status plan_any(const exs_job* job, Arena& ar, std::vector<Rec>* out,
+                           const TuneCfg& cfg) {
+    const bool sum = job->op == EXS_SUM;
+    switch (job->dtype) {
+        case EXS_F32:
+            return sum ? plan_into<float, OpSum>(job, ar, out, cfg)
+                       : plan_into<float, OpMax>(job, ar, out, cfg);
+        case EXS_F64:
+            return sum ? plan_into<double, OpSum>(job, ar, out, cfg)
+                       : plan_into<double, OpMax>(job, ar, out, cfg);
+        case EXS_I32:
+            return sum ? plan_into<int, OpSum>(job, ar, out, cfg)
+                       : plan_into<int, OpMax>(job, ar, out, cfg);
+        case EXS_I64:
+            return sum ? plan_into<long long, OpSum>(job, ar, out, cfg)
+                       : plan_into<long long, OpMax>(job, ar, out, cfg);
+    }
+    return set_error(EXS_EINVAL, "unknown dtype");
+}
+
+struct Launch {
+    int dtype, op, kind, kb;
+    size_t first;  // index of the first step in the device array
+    int nsteps;
+    i64 total;
+};
+
+}  // namespace exs
+
 using namespace exs;
+
+struct exs_batch {
+    std::vector<exs_job> jobs;
+    std::vector<size_t> ws_off;
+    size_t ws_total = 0;
+    TuneCfg cfg;
+    int num_cu = 256;
+    // built for one workspace
+    void* ws_base = nullptr;
+    std::vector<std::vector<Launch>> phases;
+    Step* dev_steps = nullptr;
+    size_t dev_cap = 0;
+    i64 items = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_nodes = 0;
+};
+
+namespace exs {
+
+static void drop_graph(exs_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_nodes = 0;
+}
+
+// Record every job's steps for workspace `ws`, group them into phases and
+// upload the step array.
+static exs_status build(exs_batch* b, void* ws, const TuneCfg& cfg) {
+    std::vector<std::vector<Rec>> recs(b->jobs.size());
+    size_t maxlen = 0;
+    for (size_t j = 0; j < b->jobs.size(); ++j) {
+        Arena ar;
+        ar.dry = false;
+        ar.base = (char*)ws + b->ws_off[j];
+        exs_status s = plan_any(&b->jobs[j], ar, &recs[j], cfg);
+        if (s != EXS_OK) return s;
+        maxlen = std::max(maxlen, recs[j].size());
+    }
+    std::vector<Step> all;
+    b->phases.assign(maxlen, {});
+    b->items = 0;
+    for (size_t p = 0; p < maxlen; ++p) {
+        std::map<std::tuple<int, int, int, int>, std::vector<const Rec*>> groups;
+        for (auto& r : recs)
+            if (p < r.size())
+                groups[std::make_tuple(r[p].dtype, r[p].op, r[p].s.kind, r[p].kb)].push_back(&r[p]);
+        for (auto& g : groups) {
+            Launch L;
+            L.dtype = std::get<0>(g.first);
+            L.op = std::get<1>(g.first);
+            L.kind = std::get<2>(g.first);
+            L.kb = std::get<3>(g.first);
+            L.first = all.size();
+            L.nsteps = (int)g.second.size();
+            i64 tb = 0;
+            for (const Rec* r : g.second) {
+                Step s = r->s;
+                s.task_begin = tb;
+                tb += s.ntasks;
+                all.push_back(s);
+            }
+            L.total = tb;
+            b->items += (i64)g.second.size();
+            b->phases[p].push_back(L);
+        }
+    }
+    const size_t bytes = all.size() * sizeof(Step);
+    if (bytes > b->dev_cap) {
+        if (b->dev_steps) (void)hipFree(b->dev_steps);
+        b->dev_steps = nullptr;
+        b->dev_cap = 0;
+        if (hipMalloc(&b->dev_steps, bytes) != hipSuccess)
+            return set_error(EXS_ENOMEM, "cannot allocate the batch step table");
+        b->dev_cap = bytes;
+    }
+    if (bytes && hipMemcpy(b->dev_steps, all.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
+        return set_error(EXS_EDEVICE, "cannot upload the batch step table");
+    b->ws_base = ws;
+    return EXS_OK;
+}
+
+static void enqueue(exs_batch* b, const TuneCfg& cfg, hipStream_t st) {
+    const i64 cap = (i64)cfg.wg_per_cu * b->num_cu;
+    for (auto& ph : b->phases)
+        for (auto& L : ph) {
+            i64 g = (L.total + 255) / 256;
+            if (g > cap) g = cap;
+            if (g < 1) g = 1;
+            launch_worklist(L.dtype, L.op, L.kind, L.kb, b->dev_steps + L.first, L.nsteps, L.total,
+                            (int)g, st);
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Autotune cache: {"version": 1, "entries": {"<sig>": {"min_tasks": .., ..}}}
+// ---------------------------------------------------------------------------
+static std::string signature(const std::vector<exs_job>& jobs) {
+    uint64_t h = 1469598103934665603ULL;  // FNV-1a over the shape description
+    auto mix = [&](int64_t v) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (uint64_t)((v >> (8 * i)) & 0xff);
+            h *= 1099511628211ULL;
+        }
+    };
+    for (auto& j : jobs) {
+        mix(j.d);
+        mix(j.dtype);
+        mix(j.op);
+        mix(j.mode);
+        for (int i = 0; i < j.d; ++i) {
+            mix(j.dims[i]);
+            mix(j.box[i]);
+        }
+    }
+    char buf[40];
+    std::snprintf(buf, sizeof(buf), "batch-%016llx-n%zu", (unsigned long long)h, jobs.size());
+    return buf;
+}
+
+static std::map<std::string, std::string> read_cache(const char* path) {
+    std::map<std::string, std::string> m;
+    std::ifstream f(path);
+    if (!f) return m;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string t = ss.str();
+    size_t p = 0;
+    while ((p = t.find("\"batch-", p)) != std::string::npos) {
+        const size_t e = t.find('"', p + 1);
+        const size_t ob = t.find('{', e);
+        const size_t cb = t.find('}', ob);
+        if (e == std::string::npos || ob == std::string::npos || cb == std::string::npos) break;
+        m[t.substr(p + 1, e - p - 1)] = t.substr(ob, cb - ob + 1);
+        p = cb;
+    }
+    return m;
+}
+
+static bool parse_field(const std::string& obj, const char* key, double* v) {
+    const std::string k = std::string("\"") + key + "\"";
+    const size_t p = obj.find(k);
+    if (p == std::string::npos) return false;
+    const size_t c = obj.find(':', p);
+    if (c == std::string::npos) return false;
+    *v = std::strtod(obj.c_str() + c + 1, nullptr);
+    return true;
+}
+
+static void write_cache(const char* path, const std::map<std::string, std::string>& m) {
+    const std::string tmp = std::string(path) + ".tmp";
+    std::ofstream f(tmp);
+    if (!f) return;
+    f << "{\n  \"version\": 1,\n  \"entries\": {\n";
+    size_t i = 0;
+    for (auto& kv : m) {
+        f << "    \"" << kv.first << "\": " << kv.second << (++i < m.size() ? ",\n" : "\n");
+    }
+    f << "  }\n}\n";
+    f.close();
+    std::rename(tmp.c_str(), path);
+}
+
+static exs_status autotune(exs_batch* b, const char* path) {
+    const std::string sig = signature(b->jobs);
+    auto cache = read_cache(path);
+    auto it = cache.find(sig);
+    if (it != cache.end()) {
+        double mt = 0, wg = 0;
+        if (parse_field(it->second, "min_tasks", &mt) && parse_field(it->second, "wg_per_cu", &wg)) {
+            b->cfg.min_tasks = (i64)mt;
+            b->cfg.wg_per_cu = (int)wg;
+            return EXS_OK;
+        }
+    }
+    void* ws = nullptr;
+    if (b->ws_total && hipMalloc(&ws, b->ws_total) != hipSuccess)
+        return set_error(EXS_ENOMEM, "cannot allocate the autotuning workspace");
+    hipStream_t st;
+    if (hipStreamCreate(&st) != hipSuccess) {
+        if (ws) (void)hipFree(ws);
+        return set_error(EXS_EDEVICE, "hipStreamCreate failed");
+    }
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const i64 mts[] = {4096, 16384, 65536};
+    const int wgs[] = {2, 4, 8};
+    TuneCfg best = b->cfg;
+    float best_ms = 1e30f;
+    exs_status rc = EXS_OK;
+    for (i64 mt : mts)
+        for (int wg : wgs) {
+            TuneCfg c;
+            c.min_tasks = mt;
+            c.wg_per_cu = wg;
+            rc = build(b, ws, c);
+            if (rc != EXS_OK) break;
+            enqueue(b, c, st);  // warm-up
+            (void)hipEventRecord(e0, st);
+            for (int r = 0; r < 3; ++r) enqueue(b, c, st);
+            (void)hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                rc = set_error(EXS_EDEVICE, "autotuning run failed");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms /= 3.f;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+    if (ws) (void)hipFree(ws);
+    b->ws_base = nullptr;  // the tuning build pointed into the freed workspace
+    if (rc != EXS_OK) return rc;
+    b->cfg = best;
+    char obj[160];
+    std::snprintf(obj, sizeof(obj), "{\"min_tasks\": %lld, \"wg_per_cu\": %d, \"ms\": %.4f}",
+                  (long long)best.min_tasks, best.wg_per_cu, best_ms);
+    cache[sig] = obj;
+    write_cache(path, cache);
+    return EXS_OK;
+}
+
+}  // namespace exs
+
 extern "C" {
-exs_status exs_batch_create(const exs_job*, int32_t, const char*, exs_batch**) {
-    return set_error(EXS_EUNSUPPORTED, "batched form not built yet");
+
+exs_status exs_batch_create(const exs_job* jobs, int32_t n, const char* tune_cache,
+                            exs_batch** out) {
+    if (!out) return set_error(EXS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !jobs) return set_error(EXS_EINVAL, "a batch needs at least one job");
+    exs_batch* b = new (std::nothrow) exs_batch();
+    if (!b) return set_error(EXS_ENOMEM, "out of host memory");
+    b->jobs.assign(jobs, jobs + n);
+    size_t off = 0;
+    for (int j = 0; j < n; ++j) {
+        exs_status s = validate_job(&b->jobs[j], true);
+        if (s != EXS_OK) {
+            delete b;
+            return set_error(s, "job " + std::to_string(j) + ": " + exs_last_error());
+        }
+        Arena ar;
+        ar.dry = true;
+        std::vector<Rec> none;
+        s = plan_any(&b->jobs[j], ar, &none, b->cfg);
+        if (s != EXS_OK) {
+            delete b;
+            return s;
+        }
+        b->ws_off.push_back(off);
+        off += (ar.off + 255) & ~(size_t)255;
+    }
+    b->ws_total = off;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            cu > 0)
+            b->num_cu = cu;
+    }
+    if (tune_cache) {
+        exs_status s = autotune(b, tune_cache);
+        if (s != EXS_OK) {
+            exs_batch_destroy(b);
+            return s;
+        }
+    }
+    *out = b;
+    return EXS_OK;
 }
-exs_status exs_batch_workspace_size(const exs_batch*, size_t*) {
-    return set_error(EXS_EUNSUPPORTED, "batched form not built yet");
+
+exs_status exs_batch_workspace_size(const exs_batch* b, size_t* bytes) {
+    if (!b || !bytes) return set_error(EXS_EINVAL, "NULL argument");
+    *bytes = b->ws_total;
+    return EXS_OK;
 }
-exs_status exs_batch_launch(exs_batch*, void*, size_t, void*) {
-    return set_error(EXS_EUNSUPPORTED, "batched form not built yet");
+
+static exs_status check_ws(exs_batch* b, void* ws, size_t ws_bytes) {
+    if (ws_bytes < b->ws_total)
+        return set_error(EXS_ENOMEM, "batch workspace too small: need " +
+                                         std::to_string(b->ws_total) + " bytes");
+    if (b->ws_total && !ws) return set_error(EXS_EINVAL, "ws is NULL");
+    if (((uintptr_t)ws & 255) != 0) return set_error(EXS_EINVAL, "ws must be 256-byte aligned");
+    if (ws != b->ws_base || b->phases.empty()) {
+        drop_graph(b);
+        exs_status s = build(b, ws, b->cfg);
+        if (s != EXS_OK) return s;
+    }
+    return EXS_OK;
 }
-exs_status exs_batch_launch_eager(exs_batch*, void*, size_t, void*) {
-    return set_error(EXS_EUNSUPPORTED, "batched form not built yet");
+
+exs_status exs_batch_launch_eager(exs_batch* b, void* ws, size_t ws_bytes, void* stream) {
+    if (!b) return set_error(EXS_EINVAL, "batch is NULL");
+    exs_status s = check_ws(b, ws, ws_bytes);
+    if (s != EXS_OK) return s;
+    enqueue(b, b->cfg, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(EXS_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
+    return EXS_OK;
 }
-exs_status exs_batch_info(const exs_batch*, int32_t*, int64_t*) {
-    return set_error(EXS_EUNSUPPORTED, "batched form not built yet");
+
+exs_status exs_batch_launch(exs_batch* b, void* ws, size_t ws_bytes, void* stream) {
+    if (!b) return set_error(EXS_EINVAL, "batch is NULL");
+    exs_status s = check_ws(b, ws, ws_bytes);
+    if (s != EXS_OK) return s;
+    if (!b->exec) {
+        if (!b->cap_stream && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
+            return set_error(EXS_EDEVICE, "hipStreamCreate failed");
+        if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return set_error(EXS_EDEVICE, "hipStreamBeginCapture failed");
+        enqueue(b, b->cfg, b->cap_stream);
+        hipGraph_t g = nullptr;
+        if (hipStreamEndCapture(b->cap_stream, &g) != hipSuccess || !g)
+            return set_error(EXS_EDEVICE, "hipStreamEndCapture failed");
+        b->graph = g;
+        size_t nn = 0;
+        if (hipGraphGetNodes(g, nullptr, &nn) == hipSuccess) b->graph_nodes = (int)nn;
+        if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            drop_graph(b);
+            return set_error(EXS_EDEVICE, "hipGraphInstantiate failed");
+        }
+    }
+    if (hipGraphLaunch(b->exec, (hipStream_t)stream) != hipSuccess)
+        return set_error(EXS_EDEVICE, "hipGraphLaunch failed");
+    return EXS_OK;
 }
-void exs_batch_destroy(exs_batch*) {}
-exs_status exs_server_create(size_t, int32_t, exs_server**) {
-    return set_error(EXS_EUNSUPPORTED, "serving form not built yet");
+
+exs_status exs_batch_info(const exs_batch* b, int32_t* graph_nodes, int64_t* work_items) {
+    if (!b) return set_error(EXS_EINVAL, "batch is NULL");
+    if (graph_nodes) *graph_nodes = b->graph_nodes;
+    if (work_items) *work_items = b->items;
+    return EXS_OK;
 }
-exs_status exs_server_submit(exs_server*, const exs_job*, uint64_t*) {
-    return set_error(EXS_EUNSUPPORTED, "serving form not built yet");
+
+void exs_batch_destroy(exs_batch* b) {
+    if (!b) return;
+    drop_graph(b);
+    if (b->dev_steps) (void)hipFree(b->dev_steps);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    delete b;
 }
-exs_status exs_server_poll(exs_server*, uint64_t, const void**, const void**, double*) {
-    return set_error(EXS_EUNSUPPORTED, "serving form not built yet");
-}
-exs_status exs_server_drain(exs_server*) {
-    return set_error(EXS_EUNSUPPORTED, "serving form not built yet");
-}
-exs_status exs_server_release(exs_server*, uint64_t) {
-    return set_error(EXS_EUNSUPPORTED, "serving form not built yet");
-}
-exs_status exs_server_stats(exs_server*, double*, double*, double*, double*, int64_t*, int64_t*,
-                            int64_t*) {
-    return set_error(EXS_EUNSUPPORTED, "serving form not built yet");
-}
-void exs_server_destroy(exs_server*) {}
-}
+
+}  // extern "C"

@@ -13,6 +13,23 @@ namespace exs {
 struct OpSum;
 struct OpMax;
 
+// register bucket (power of two >= k, up to 64) of a box length; 0 = none
+inline int bucket_for(i64 k) {
+    if (k <= 1) return 1;
+    if (k <= 2) return 2;
+    if (k <= 4) return 4;
+    if (k <= 8) return 8;
+    if (k <= 16) return 16;
+    if (k <= 32) return 32;
+    if (k <= 64) return 64;
+    return 0;
+}
+
+// work-list launch of the batched form (exsum_worklist.hip): `steps` is a
+// device array of Step (exsum_tasks.hpp)
+void launch_worklist(int dtype, int op, int kind, int kb, const void* steps, int nsteps, i64 total,
+                     int grid, hipStream_t st);
+
 // generic-path launchers (exsum_kernels.hip)
 template <typename T, class Op>
 void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st);

@@ -17,80 +17,33 @@
 //                   Contribution").
 //   k_ex1d_2sweep   the axis-0 excluded part for boxes longer than 64.
 //   k_fill          counter-based input generator (workload support).
-#include "exsum_device.hpp"
 #include "exsum_internal.hpp"
+#include "exsum_tasks.hpp"
 
 namespace exs {
 
-// ---------------------------------------------------------------------------
-// BDBS along an axis of a tensor viewed as (O, n, I).  Threads map to
-// (o, chunk, i) with i fastest, so loads and stores are coalesced whenever
-// I >= 64; each thread streams `cb` blocks of its row.
-// ---------------------------------------------------------------------------
+// Plain kernels: one thread per task of one step (exsum_tasks.hpp).
 template <typename T, class Op, int KB>
 __global__ __launch_bounds__(256) void k_bdbs(const T* __restrict__ in, T* __restrict__ out,
                                               i64 O, i64 n, i64 I, int k, i64 cb,
                                               i64 nchunks) {
     const i64 idx = gtid();
-    if (idx >= O * nchunks * I) return;
-    const i64 i = idx % I;
-    const i64 rest = idx / I;
-    const i64 c = rest % nchunks;
-    const i64 o = rest / nchunks;
-    const i64 nb = (n + k - 1) / k;
-    const i64 b0 = c * cb;
-    if (b0 >= nb) return;
-    const i64 b1 = b0 + cb < nb ? b0 + cb : nb;
-    const i64 off = o * n * I + i;
-    bdbs_row<T, Op, KB>(in + off, out + off, n, I, k, b0, b1);
+    if (idx < O * nchunks * I) task_bdbs<T, Op, KB>(in, out, O, n, I, k, cb, nchunks, idx);
 }
 
-// Two-sweep BDBS for k > 64: the backward sweep writes the range suffixes,
-// the forward sweep adds the range prefix of the next block (out != in).
 template <typename T, class Op>
 __global__ __launch_bounds__(256) void k_bdbs_2sweep(const T* __restrict__ in,
                                                      T* __restrict__ out, i64 O, i64 n,
                                                      i64 I, i64 k) {
     const i64 idx = gtid();
-    if (idx >= O * I) return;
-    const i64 i = idx % I, o = idx / I;
-    const T* src = in + o * n * I + i;
-    T* dst = out + o * n * I + i;
-    const T e = Op::template id<T>();
-    T rs = e;
-    for (i64 x = n - 1; x >= 0; --x) {
-        const bool last = (x % k == k - 1) || (x == n - 1);
-        rs = last ? src[x * I] : Op::apply(src[x * I], rs);
-        dst[x * I] = rs;
-    }
-    T rp = e;
-    for (i64 t = 0; t < n; ++t) {
-        rp = (t % k == 0) ? src[t * I] : Op::apply(rp, src[t * I]);
-        const i64 x = t - k + 1;
-        if (x >= 0 && x % k != 0) dst[x * I] = Op::apply(dst[x * I], rp);
-    }
-    // windows whose next block is the partial last block and reach past n
-    const i64 L = (n - 1) / k, Ls = L * k;
-    if (L >= 1) {
-        i64 lo = Ls - k + 1;
-        if (n - k + 1 > lo) lo = n - k + 1;
-        for (i64 x = lo; x < Ls; ++x) dst[x * I] = Op::apply(dst[x * I], rp);
-    }
+    if (idx < O * I) task_bdbs2<T, Op>(in, out, n, I, k, idx);
 }
 
-// Ga[q, m] = op over t in block q of X[t, m]; X viewed as (n0, M).
 template <typename T, class Op>
 __global__ __launch_bounds__(256) void k_blockagg(const T* __restrict__ X, T* __restrict__ Ga,
                                                   i64 n0, i64 M, i64 k0, i64 Q) {
     const i64 idx = gtid();
-    if (idx >= Q * M) return;
-    const i64 m = idx % M, q = idx / M;
-    const i64 t0 = q * k0;
-    const i64 t1 = t0 + k0 < n0 ? t0 + k0 : n0;
-    T s = Op::template id<T>();
-#pragma unroll 8
-    for (i64 t = t0; t < t1; ++t) s = Op::apply(s, X[t * M + m]);
-    Ga[idx] = s;
+    if (idx < Q * M) task_agg<T, Op>(X, Ga, n0, M, k0, idx);
 }
 
 // The same for 4-byte elements with M % 4 == 0: each thread owns 4
@@ -139,35 +92,15 @@ __global__ __launch_bounds__(256) void k_blockagg4(const T* __restrict__ X, T* _
     ((uint4*)Ga)[q * M4 + m4] = o;
 }
 
-// Per point m: PX[q] = op of Gw[q'] for q' < q, SX[q] = op of Gw[q'] for
-// q' > q, R[m] = op over all blocks of Ga (the reduction of axis 0).
 template <typename T, class Op>
 __global__ __launch_bounds__(256) void k_blockscan(const T* __restrict__ Gw,
                                                    const T* __restrict__ Ga,
                                                    T* __restrict__ PX, T* __restrict__ SX,
                                                    T* __restrict__ R, i64 Q, i64 M) {
     const i64 m = gtid();
-    if (m >= M) return;
-    const T e = Op::template id<T>();
-    T p = e, r = e;
-#pragma unroll 8
-    for (i64 q = 0; q < Q; ++q) {
-        PX[q * M + m] = p;
-        p = Op::apply(p, Gw[q * M + m]);
-        r = Op::apply(r, Ga[q * M + m]);
-    }
-    T s = e;
-#pragma unroll 8
-    for (i64 q = Q - 1; q >= 0; --q) {
-        SX[q * M + m] = s;
-        s = Op::apply(Gw[q * M + m], s);
-    }
-    if (R) R[m] = r;
+    if (m < M) task_scan<T, Op>(Gw, Ga, PX, SX, R, Q, M, m);
 }
 
-// Axis-0 stream for the generic path.  Threads map to (segment, m), m
-// fastest; each thread owns one point m and a run of blocks [qa, qb) of
-// axis 0, reading one block ahead.
 template <typename T, class Op, int K0B>
 __global__ __launch_bounds__(256) void k_axis0(const T* __restrict__ W, const T* __restrict__ PX,
                                                const T* __restrict__ SX,
@@ -175,86 +108,17 @@ __global__ __launch_bounds__(256) void k_axis0(const T* __restrict__ W, const T*
                                                T* __restrict__ inc, i64 n0, i64 M, int k0,
                                                i64 Q, i64 segblocks, i64 nseg) {
     const i64 idx = gtid();
-    if (idx >= nseg * M) return;
-    const i64 m = idx % M, s = idx / M;
-    const i64 qa = s * segblocks;
-    if (qa >= Q) return;
-    const i64 qb = qa + segblocks < Q ? qa + segblocks : Q;
-    const bool do_ex = exc != nullptr, do_inc = inc != nullptr;
-    const T e = Op::template id<T>();
-    const T* src = W + m;
-
-    Axis0State<T, Op, K0B> st;
-    T v[K0B];
-#pragma unroll
-    for (int r = 0; r < K0B; ++r) {
-        const i64 x = qa * k0 + r;
-        v[r] = (r < k0 && x < n0) ? src[x * M] : e;
-    }
-    st.P = e;
-    if (do_ex) {
-        st.P = PX[qa * M + m];
-        if (Trest) st.P = Op::apply(st.P, Trest[m]);
-    }
-    st.absorb(v, k0, do_ex, do_inc);
-
-    for (i64 q = qa; q < qb; ++q) {
-        const i64 nbase = (q + 1) * k0;
-#pragma unroll
-        for (int r = 0; r < K0B; ++r) {
-            const i64 x = nbase + r;
-            v[r] = (r < k0 && x < n0) ? src[x * M] : e;
-        }
-        if (do_ex) {
-            T S = (q + 1 < Q) ? SX[(q + 1) * M + m] : e;
-#pragma unroll
-            for (int r = K0B - 1; r >= 0; --r) {
-                if (r < k0) {
-                    S = Op::apply(v[r], S);
-                    const i64 x = q * k0 + r;
-                    if (x < n0) exc[x * M + m] = Op::apply(st.pex[r], S);
-                }
-            }
-        }
-        if (do_inc) {
-            T p = e;
-#pragma unroll
-            for (int r = 0; r < K0B; ++r) {
-                if (r < k0) {
-                    T val = st.rs[r];
-                    if (r > 0) { p = Op::apply(p, v[r - 1]); val = Op::apply(val, p); }
-                    const i64 x = q * k0 + r;
-                    if (x < n0) inc[x * M + m] = val;
-                }
-            }
-        }
-        if (q + 1 < qb) st.absorb(v, k0, do_ex, do_inc);
-    }
+    if (idx < nseg * M)
+        task_axis0<T, Op, K0B>(W, PX, SX, Trest, exc, inc, n0, M, k0, Q, segblocks, idx);
 }
 
-// Axis-0 excluded part for k0 > 64, one thread per point, two sweeps:
-// the backward sweep stores the suffix from x0 + k0, the forward sweep
-// prepends the prefix before x0 and the lower-dimensional term.
 template <typename T, class Op>
 __global__ __launch_bounds__(256) void k_ex1d_2sweep(const T* __restrict__ W,
                                                      const T* __restrict__ Trest,
                                                      T* __restrict__ exc, i64 n0, i64 M,
                                                      i64 k0) {
     const i64 m = gtid();
-    if (m >= M) return;
-    const T e = Op::template id<T>();
-    for (i64 x = n0 - k0; x < n0; ++x)
-        if (x >= 0) exc[x * M + m] = e;
-    T S = e;
-    for (i64 t = n0 - 1; t >= 0; --t) {
-        S = Op::apply(W[t * M + m], S);
-        if (t - k0 >= 0) exc[(t - k0) * M + m] = S;
-    }
-    T P = Trest ? Trest[m] : e;
-    for (i64 x = 0; x < n0; ++x) {
-        exc[x * M + m] = Op::apply(P, exc[x * M + m]);
-        P = Op::apply(P, W[x * M + m]);
-    }
+    if (m < M) task_ex2<T, Op>(W, Trest, exc, n0, M, k0, m);
 }
 
 // ---------------------------------------------------------------------------
@@ -298,16 +162,6 @@ static inline unsigned grid_for(i64 threads, int block = 256) {
     return (unsigned)(g < 1 ? 1 : g);
 }
 
-static inline int bucket_for(i64 k) {
-    if (k <= 1) return 1;
-    if (k <= 2) return 2;
-    if (k <= 4) return 4;
-    if (k <= 8) return 8;
-    if (k <= 16) return 16;
-    if (k <= 32) return 32;
-    if (k <= 64) return 64;
-    return 0;
-}
 
 template <typename T, class Op>
 void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st) {

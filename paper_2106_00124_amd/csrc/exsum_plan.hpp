@@ -1,0 +1,190 @@
+// exsum_plan.hpp -- the planner of included/excluded sums for one tensor.
+//
+// Paper: Xu, Fraser, Leiserson, "Multidimensional Included and Excluded Sums"
+// (SIAM ACDA 2021, arXiv 2106.00124).
+//
+// Excluded sums follow the box-complement algorithm (Sec. 5) in its
+// dimension-reduction form.  With R_0 = A and R_{j+1} = the reduction of R_j
+// over its first axis, the excluded sum of R_j (rank d_j) is
+//
+//   Exc_j(x) = Ex1D_0( Inc_{1..}(R_j) )(x) op Exc_{j+1}(x_1, ..., x_{d_j-1})
+//
+// where Inc_{1..} box-sums every axis but the first (BDBS-Along-Dim, Sec. 5)
+// and Ex1D_0 is the op of the prefix before x_0 and the suffix from x_0+k_0
+// along the first axis (Prefix-/Suffix-Along-Dim, Sec. 5).  The two components
+// of step j+1 in Corollary "Excluded-sum Components" are exactly the prefix
+// and suffix terms; the lower-dimensional term carries the components of the
+// later steps, broadcast over the reduced axes (Add-Contribution, Sec. 5).
+// Included sums are BDBS along every axis (Sec. 3, "Generalizing to
+// Arbitrary Dimensions").
+//
+// The planner emits its steps into a Sink: EagerSink launches each step on a
+// stream (the plain call); the batched form records them into work lists.
+// Buffers come from an Arena over the caller's workspace; in "dry" mode the
+// arena only measures, so sizing and execution share one code path.
+#pragma once
+#include <algorithm>
+
+#include "exsum_internal.hpp"
+
+namespace exs {
+
+// Bump allocator over the caller's workspace.  In "dry" mode it only
+// measures, so sizing and execution share one code path.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, off = 0;
+    bool dry = true;
+    template <typename T>
+    T* take(i64 count) {
+        off = (off + 255) & ~(size_t)255;
+        T* p = dry ? nullptr : (T*)(base + off);
+        off += (size_t)count * sizeof(T);
+        return p;
+    }
+};
+
+inline i64 prod(const i64* v, int a, int b) {
+    i64 p = 1;
+    for (int i = a; i < b; ++i) p *= v[i];
+    return p;
+}
+
+// Box-sum a rank-d tensor over axes last .. first (last axis first: the
+// innermost reduction of the nested definition in Sec. 2), ping-ponging
+// between wb[0] and wb[1].  Returns the result (src itself if no axis).
+template <typename T, class Sink>
+static const T* filter_axes(const T* src, const i64* n, const i64* k, int d, int first, int last,
+                            T* wb0, T* wb1, bool dry, Sink& sink) {
+    const T* cur = src;
+    T* wb[2] = {wb0, wb1};
+    int which = 0;
+    for (int a = last; a >= first; --a) {
+        T* dst = wb[which];
+        which ^= 1;
+        if (!dry) sink.bdbs(cur, dst, prod(n, 0, a), n[a], prod(n, a + 1, d), k[a]);
+        cur = dst;
+    }
+    return cur;
+}
+
+template <typename T, class Sink>
+static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
+    const int d = job->d;
+    i64 n[EXS_MAX_RANK], k[EXS_MAX_RANK];
+    for (int i = 0; i < d; ++i) { n[i] = job->dims[i]; k[i] = job->box[i]; }
+    const T* A = (const T*)job->in_dev;
+    T* inc = (job->mode & EXS_INCLUDED) ? (T*)job->inc_out_dev : nullptr;
+    T* exc = (job->mode & EXS_EXCLUDED) ? (T*)job->exc_out_dev : nullptr;
+    const bool want_exc = job->mode & EXS_EXCLUDED;
+    const bool dry = ar.dry;
+    const i64 N = prod(n, 0, d);
+    // level 0 streams axis 0 with the fused plane kernel when it applies; it
+    // box-sums the two trailing axes itself, the middle axes are done first
+    const bool fused = sink.fused_ok && sizeof(T) == 4 && plane_eligible(d, n, k, (int)sizeof(T));
+
+    // buffers for box-summed tensors, shared by every level: level j needs
+    // (d_j - 1) passes over N_j elements, the fused level 0 only d - 3
+    int wb_count = 0;
+    i64 wb_elems = 0;
+    for (int j = 0; j < (want_exc ? d : 1); ++j) {
+        const int passes = (j == 0 && fused) ? std::max(0, d - 3) : d - j - 1;
+        if (passes > 0) {
+            wb_count = std::max(wb_count, std::min(2, passes));
+            wb_elems = std::max(wb_elems, prod(n, j, d));
+        }
+    }
+    T* wb0 = wb_count >= 1 ? ar.take<T>(wb_elems) : nullptr;
+    T* wb1 = wb_count >= 2 ? ar.take<T>(wb_elems) : nullptr;
+
+    sink.level(0);
+    if (!want_exc) {
+        // included sums only: BDBS along every axis
+        if (fused) {
+            const T* X0 = filter_axes<T>(A, n, k, d, 1, d - 3, wb0, wb1, dry, sink);
+            if (!dry)
+                sink.plane_axis0(X0, nullptr, nullptr, nullptr, nullptr, inc, n[0],
+                                 prod(n, 1, d - 2), n[d - 2], n[d - 1], k[0], k[d - 2], k[d - 1],
+                                 (n[0] + k[0] - 1) / k[0]);
+            return EXS_OK;
+        }
+        const T* W = filter_axes<T>(A, n, k, d, 1, d - 1, wb0, wb1, dry, sink);
+        if (!dry) sink.bdbs(W, inc, 1, n[0], prod(n, 1, d), k[0]);
+        return EXS_OK;
+    }
+
+    // per-level sizes
+    i64 Q[EXS_MAX_RANK], M[EXS_MAX_RANK];
+    i64 maxQM = 0;
+    for (int j = 0; j < d; ++j) {
+        Q[j] = (n[j] + k[j] - 1) / k[j];
+        M[j] = prod(n, j + 1, d);
+        maxQM = std::max(maxQM, Q[j] * M[j]);
+    }
+    T* Ga = ar.take<T>(maxQM);
+    const int ngb = std::min(2, d - 1);
+    T* gb0 = ngb >= 1 ? ar.take<T>(maxQM) : nullptr;
+    T* gb1 = ngb >= 2 ? ar.take<T>(maxQM) : nullptr;
+    T *PX[EXS_MAX_RANK], *SX[EXS_MAX_RANK], *R[EXS_MAX_RANK + 1];
+    R[0] = nullptr;
+    for (int j = 0; j < d; ++j) {
+        PX[j] = ar.take<T>(Q[j] * M[j]);
+        SX[j] = ar.take<T>(Q[j] * M[j]);
+        R[j + 1] = ar.take<T>(M[j]);
+    }
+    // lower-level excluded sums: level j >= 1 writes tb[j % 2] (N_j <= N_1)
+    T* tb0 = d >= 3 ? ar.take<T>(M[0]) : nullptr;
+    T* tb1 = d >= 2 ? ar.take<T>(M[0]) : nullptr;
+    T* tb[2] = {tb0, tb1};
+
+    // top-down: block aggregates, their box-sums over the other axes, block
+    // scans, and the reduction that feeds the next level
+    for (int j = 0; j < d; ++j) {
+        const int dj = d - j;
+        const T* src = j == 0 ? A : R[j];
+        sink.level(j);
+        if (!dry) sink.blockagg(src, Ga, n[j], M[j], k[j], Q[j]);
+        i64 gn[EXS_MAX_RANK], gk[EXS_MAX_RANK];
+        gn[0] = Q[j];
+        gk[0] = 1;
+        for (int a = 1; a < dj; ++a) { gn[a] = n[j + a]; gk[a] = k[j + a]; }
+        const T* Gw;
+        if (j == 0 && fused && plane2_eligible(n[d - 2], n[d - 1], k[d - 2], k[d - 1],
+                                               (int)sizeof(T))) {
+            // middle axes by the generic passes, the two trailing axes in one
+            // LDS-tiled pass
+            const T* G1 = filter_axes<T>(Ga, gn, gk, dj, 1, dj - 3, gb0, gb1, dry, sink);
+            T* G2 = G1 == gb0 ? gb1 : gb0;
+            if (!dry)
+                sink.plane_bdbs(G1, G2, Q[0] * prod(n, 1, d - 2), n[d - 2], n[d - 1], k[d - 2],
+                                k[d - 1]);
+            Gw = G2;
+        } else {
+            Gw = filter_axes<T>(Ga, gn, gk, dj, 1, dj - 1, gb0, gb1, dry, sink);
+        }
+        if (!dry) sink.blockscan(Gw, Ga, PX[j], SX[j], R[j + 1], Q[j], M[j]);
+    }
+    // bottom-up: stream the first axis of each level, adding the level below
+    for (int j = d - 1; j >= 0; --j) {
+        const int dj = d - j;
+        const T* src = j == 0 ? A : R[j];
+        sink.level(j);
+        T* out = j == 0 ? exc : tb[j % 2];
+        const T* Trest = j == d - 1 ? nullptr : tb[(j + 1) % 2];
+        if (j == 0 && fused) {
+            const T* X0 = filter_axes<T>(A, n, k, d, 1, d - 3, wb0, wb1, dry, sink);
+            if (!dry)
+                sink.plane_axis0(X0, PX[0], SX[0], Trest, exc, inc, n[0], prod(n, 1, d - 2),
+                                 n[d - 2], n[d - 1], k[0], k[d - 2], k[d - 1], Q[0]);
+            continue;
+        }
+        const T* W = filter_axes<T>(src, n + j, k + j, dj, 1, dj - 1, wb0, wb1, dry, sink);
+        if (!dry)
+            sink.axis0(W, PX[j], SX[j], Trest, out, j == 0 ? inc : nullptr, n[j], M[j], k[j],
+                       Q[j]);
+    }
+    return EXS_OK;
+}
+
+
+}  // namespace exs

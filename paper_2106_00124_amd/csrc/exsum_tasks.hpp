@@ -1,0 +1,233 @@
+// exsum_tasks.hpp -- per-task device functions of the generic path.
+//
+// Paper: Xu, Fraser, Leiserson, "Multidimensional Included and Excluded Sums"
+// (SIAM ACDA 2021, arXiv 2106.00124).
+//
+// Each function computes one thread-sized task of one step, identified by a
+// flat task index.  The plain kernels (exsum_kernels.hip) map one thread to
+// one task; the work-list kernels of the batched form (exsum_worklist.hip)
+// walk the tasks of many steps of many tensors with a persistent grid.  Both
+// run exactly this code, so a batched job computes what its plain call does.
+#pragma once
+#include "exsum_device.hpp"
+
+namespace exs {
+
+// Step kinds
+enum StepKind : int {
+    SK_BDBS = 0,   // BDBS along one axis, block suffixes in registers (k <= 64)
+    SK_BDBS2 = 1,  // BDBS along one axis, two sweeps (any k)
+    SK_AGG = 2,    // block aggregates along axis 0
+    SK_SCAN = 3,   // exclusive block prefix/suffix and the reduction of axis 0
+    SK_AX0 = 4,    // axis-0 stream: excluded and/or included sums (k0 <= 64)
+    SK_EX2 = 5,    // axis-0 excluded part, two sweeps (any k0)
+    SK_NKINDS = 6
+};
+
+// One step of the generic path.  Pointers are device pointers; the meaning
+// of each field depends on the kind (see make_* in exsum_plan.hpp).
+struct Step {
+    int kind;
+    int k;             // box length along the processed axis
+    const void* in0;   // bdbs/agg/ax0/ex2: input; scan: Gw
+    const void* in1;   // scan: Ga;  ax0: PX
+    const void* in2;   // ax0: SX
+    const void* in3;   // ax0/ex2: lower-dimensional excluded sums (or null)
+    void* out0;        // bdbs: out; agg: Ga; scan: PX; ax0/ex2: exc (or null)
+    void* out1;        // scan: SX; ax0: inc (or null)
+    void* out2;        // scan: R (or null)
+    i64 O, n, I;       // bdbs view (outer, axis length, inner); agg/ax0: n = n0, I = M
+    i64 Q;             // blocks along axis 0
+    i64 cb, nchunks;   // bdbs: blocks per chunk, chunks;  ax0: blocks per run, runs
+    i64 ntasks;        // tasks of this step
+    i64 task_begin;    // first flat task index of this step in its work list
+};
+
+// BDBS along an axis of a (O, n, I) tensor: task = (o, chunk, i), i fastest
+// (coalesced whenever I >= 64); each task streams `cb` blocks of its row.
+template <typename T, class Op, int KB>
+__device__ __forceinline__ void task_bdbs(const T* __restrict__ in, T* __restrict__ out, i64 O,
+                                          i64 n, i64 I, int k, i64 cb, i64 nchunks, i64 idx) {
+    const i64 i = idx % I;
+    const i64 rest = idx / I;
+    const i64 c = rest % nchunks;
+    const i64 o = rest / nchunks;
+    const i64 nb = (n + k - 1) / k;
+    const i64 b0 = c * cb;
+    if (b0 >= nb || o >= O) return;
+    const i64 b1 = b0 + cb < nb ? b0 + cb : nb;
+    const i64 off = o * n * I + i;
+    bdbs_row<T, Op, KB>(in + off, out + off, n, I, k, b0, b1);
+}
+
+// Two-sweep BDBS for any k: the backward sweep writes the range suffixes,
+// the forward sweep adds the range prefix of the next block (out != in).
+template <typename T, class Op>
+__device__ __forceinline__ void task_bdbs2(const T* __restrict__ in, T* __restrict__ out, i64 n,
+                                           i64 I, i64 k, i64 idx) {
+    const i64 i = idx % I, o = idx / I;
+    const T* src = in + o * n * I + i;
+    T* dst = out + o * n * I + i;
+    const T e = Op::template id<T>();
+    T rs = e;
+    for (i64 x = n - 1; x >= 0; --x) {
+        const bool last = (x % k == k - 1) || (x == n - 1);
+        rs = last ? src[x * I] : Op::apply(src[x * I], rs);
+        dst[x * I] = rs;
+    }
+    T rp = e;
+    for (i64 t = 0; t < n; ++t) {
+        rp = (t % k == 0) ? src[t * I] : Op::apply(rp, src[t * I]);
+        const i64 x = t - k + 1;
+        if (x >= 0 && x % k != 0) dst[x * I] = Op::apply(dst[x * I], rp);
+    }
+    // windows whose next block is the partial last block and reach past n
+    const i64 L = (n - 1) / k, Ls = L * k;
+    if (L >= 1) {
+        i64 lo = Ls - k + 1;
+        if (n - k + 1 > lo) lo = n - k + 1;
+        for (i64 x = lo; x < Ls; ++x) dst[x * I] = Op::apply(dst[x * I], rp);
+    }
+}
+
+// Ga[q, m] = op over t in block q of X[t, m]; X viewed as (n0, M); task = (q, m).
+template <typename T, class Op>
+__device__ __forceinline__ void task_agg(const T* __restrict__ X, T* __restrict__ Ga, i64 n0,
+                                         i64 M, i64 k0, i64 idx) {
+    const i64 m = idx % M, q = idx / M;
+    const i64 t0 = q * k0;
+    const i64 t1 = t0 + k0 < n0 ? t0 + k0 : n0;
+    T s = Op::template id<T>();
+#pragma unroll 8
+    for (i64 t = t0; t < t1; ++t) s = Op::apply(s, X[t * M + m]);
+    Ga[idx] = s;
+}
+
+// Per point m (= task): PX[q] = op of Gw[q'] for q' < q, SX[q] = op of Gw[q']
+// for q' > q, R[m] = op over all blocks of Ga (the reduction of axis 0).
+template <typename T, class Op>
+__device__ __forceinline__ void task_scan(const T* __restrict__ Gw, const T* __restrict__ Ga,
+                                          T* __restrict__ PX, T* __restrict__ SX,
+                                          T* __restrict__ R, i64 Q, i64 M, i64 m) {
+    const T e = Op::template id<T>();
+    T p = e, r = e;
+#pragma unroll 8
+    for (i64 q = 0; q < Q; ++q) {
+        PX[q * M + m] = p;
+        p = Op::apply(p, Gw[q * M + m]);
+        r = Op::apply(r, Ga[q * M + m]);
+    }
+    T s = e;
+#pragma unroll 8
+    for (i64 q = Q - 1; q >= 0; --q) {
+        SX[q * M + m] = s;
+        s = Op::apply(Gw[q * M + m], s);
+    }
+    if (R) R[m] = r;
+}
+
+// Axis-0 stream (generic path): task = (run, m), m fastest; the task owns
+// point m and blocks [qa, qb) of axis 0, reading one block ahead.
+template <typename T, class Op, int K0B>
+__device__ __forceinline__ void task_axis0(const T* __restrict__ W, const T* __restrict__ PX,
+                                           const T* __restrict__ SX, const T* __restrict__ Trest,
+                                           T* __restrict__ exc, T* __restrict__ inc, i64 n0,
+                                           i64 M, int k0, i64 Q, i64 segblocks, i64 idx) {
+    const i64 m = idx % M, s = idx / M;
+    const i64 qa = s * segblocks;
+    if (qa >= Q) return;
+    const i64 qb = qa + segblocks < Q ? qa + segblocks : Q;
+    const bool do_ex = exc != nullptr, do_inc = inc != nullptr;
+    const T e = Op::template id<T>();
+    const T* src = W + m;
+
+    Axis0State<T, Op, K0B> st;
+    T v[K0B];
+#pragma unroll
+    for (int r = 0; r < K0B; ++r) {
+        const i64 x = qa * k0 + r;
+        v[r] = (r < k0 && x < n0) ? src[x * M] : e;
+    }
+    st.P = e;
+    if (do_ex) {
+        st.P = PX[qa * M + m];
+        if (Trest) st.P = Op::apply(st.P, Trest[m]);
+    }
+    st.absorb(v, k0, do_ex, do_inc);
+
+    for (i64 q = qa; q < qb; ++q) {
+        const i64 nbase = (q + 1) * k0;
+#pragma unroll
+        for (int r = 0; r < K0B; ++r) {
+            const i64 x = nbase + r;
+            v[r] = (r < k0 && x < n0) ? src[x * M] : e;
+        }
+        if (do_ex) {
+            T S = (q + 1 < Q) ? SX[(q + 1) * M + m] : e;
+#pragma unroll
+            for (int r = K0B - 1; r >= 0; --r) {
+                if (r < k0) {
+                    S = Op::apply(v[r], S);
+                    const i64 x = q * k0 + r;
+                    if (x < n0) exc[x * M + m] = Op::apply(st.pex[r], S);
+                }
+            }
+        }
+        if (do_inc) {
+            T p = e;
+#pragma unroll
+            for (int r = 0; r < K0B; ++r) {
+                if (r < k0) {
+                    T val = st.rs[r];
+                    if (r > 0) { p = Op::apply(p, v[r - 1]); val = Op::apply(val, p); }
+                    const i64 x = q * k0 + r;
+                    if (x < n0) inc[x * M + m] = val;
+                }
+            }
+        }
+        if (q + 1 < qb) st.absorb(v, k0, do_ex, do_inc);
+    }
+}
+
+// Axis-0 excluded part for any k0, one task per point, two sweeps: the
+// backward sweep stores the suffix from x0 + k0, the forward sweep prepends
+// the prefix before x0 and the lower-dimensional term.
+template <typename T, class Op>
+__device__ __forceinline__ void task_ex2(const T* __restrict__ W, const T* __restrict__ Trest,
+                                         T* __restrict__ exc, i64 n0, i64 M, i64 k0, i64 m) {
+    const T e = Op::template id<T>();
+    for (i64 x = n0 - k0; x < n0; ++x)
+        if (x >= 0) exc[x * M + m] = e;
+    T S = e;
+    for (i64 t = n0 - 1; t >= 0; --t) {
+        S = Op::apply(W[t * M + m], S);
+        if (t - k0 >= 0) exc[(t - k0) * M + m] = S;
+    }
+    T P = Trest ? Trest[m] : e;
+    for (i64 x = 0; x < n0; ++x) {
+        exc[x * M + m] = Op::apply(P, exc[x * M + m]);
+        P = Op::apply(P, W[x * M + m]);
+    }
+}
+
+// Dispatch one task of a recorded step (KB: the register bucket of the step,
+// for the kinds that have one).
+template <typename T, class Op, int KIND, int KB>
+__device__ __forceinline__ void run_task(const Step& s, i64 i) {
+    if constexpr (KIND == SK_BDBS)
+        task_bdbs<T, Op, KB>((const T*)s.in0, (T*)s.out0, s.O, s.n, s.I, s.k, s.cb, s.nchunks, i);
+    else if constexpr (KIND == SK_BDBS2)
+        task_bdbs2<T, Op>((const T*)s.in0, (T*)s.out0, s.n, s.I, s.k, i);
+    else if constexpr (KIND == SK_AGG)
+        task_agg<T, Op>((const T*)s.in0, (T*)s.out0, s.n, s.I, s.k, i);
+    else if constexpr (KIND == SK_SCAN)
+        task_scan<T, Op>((const T*)s.in0, (const T*)s.in1, (T*)s.out0, (T*)s.out1, (T*)s.out2,
+                         s.Q, s.I, i);
+    else if constexpr (KIND == SK_AX0)
+        task_axis0<T, Op, KB>((const T*)s.in0, (const T*)s.in1, (const T*)s.in2, (const T*)s.in3,
+                              (T*)s.out0, (T*)s.out1, s.n, s.I, s.k, s.Q, s.cb, i);
+    else
+        task_ex2<T, Op>((const T*)s.in0, (const T*)s.in3, (T*)s.out0, s.n, s.I, s.k, i);
+}
+
+}  // namespace exs

@@ -1,0 +1,81 @@
+// exsum_worklist.hip -- persistent work-list kernels of the batched form.
+//
+// Paper: Xu, Fraser, Leiserson, "Multidimensional Included and Excluded Sums"
+// (SIAM ACDA 2021, arXiv 2106.00124).
+//
+// One launch covers one kind of step (with one dtype, operator and register
+// bucket) for many tensors at once.  The steps of the launch sit in a device
+// array ordered by task_begin; a persistent grid walks the flat task range
+// [0, total) with a grid stride, finds each task's step by binary search and
+// runs the same per-task function as the plain kernels.
+#include "exsum_internal.hpp"
+#include "exsum_tasks.hpp"
+
+namespace exs {
+
+template <typename T, class Op, int KIND, int KB>
+__global__ __launch_bounds__(256) void k_worklist(const Step* __restrict__ steps, int nsteps,
+                                                  i64 total) {
+    const i64 stride = (i64)gridDim.x * blockDim.x;
+    for (i64 t = gtid(); t < total; t += stride) {
+        int lo = 0, hi = nsteps - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (steps[mid].task_begin <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const Step s = steps[lo];
+        run_task<T, Op, KIND, KB>(s, t - s.task_begin);
+    }
+}
+
+template <typename T, class Op, int KIND>
+static void launch_kb(int kb, const Step* steps, int nsteps, i64 total, int grid, hipStream_t st) {
+#define EXS_WL(KB)                                                                            \
+    case KB:                                                                                  \
+        hipLaunchKernelGGL((k_worklist<T, Op, KIND, KB>), dim3(grid), dim3(256), 0, st, steps, \
+                           nsteps, total);                                                    \
+        return;
+    if constexpr (KIND == SK_BDBS || KIND == SK_AX0) {
+        switch (kb) {
+            EXS_WL(1) EXS_WL(2) EXS_WL(4) EXS_WL(8) EXS_WL(16) EXS_WL(32) EXS_WL(64)
+        }
+    } else {
+        hipLaunchKernelGGL((k_worklist<T, Op, KIND, 1>), dim3(grid), dim3(256), 0, st, steps,
+                           nsteps, total);
+    }
+#undef EXS_WL
+}
+
+template <typename T, class Op>
+static void launch_kind(int kind, int kb, const Step* steps, int nsteps, i64 total, int grid,
+                        hipStream_t st) {
+    switch (kind) {
+        case SK_BDBS: launch_kb<T, Op, SK_BDBS>(kb, steps, nsteps, total, grid, st); break;
+        case SK_BDBS2: launch_kb<T, Op, SK_BDBS2>(kb, steps, nsteps, total, grid, st); break;
+        case SK_AGG: launch_kb<T, Op, SK_AGG>(kb, steps, nsteps, total, grid, st); break;
+        case SK_SCAN: launch_kb<T, Op, SK_SCAN>(kb, steps, nsteps, total, grid, st); break;
+        case SK_AX0: launch_kb<T, Op, SK_AX0>(kb, steps, nsteps, total, grid, st); break;
+        case SK_EX2: launch_kb<T, Op, SK_EX2>(kb, steps, nsteps, total, grid, st); break;
+    }
+}
+
+template <typename T>
+static void launch_op(int op, int kind, int kb, const Step* steps, int nsteps, i64 total, int grid,
+                      hipStream_t st) {
+    if (op == EXS_SUM) launch_kind<T, OpSum>(kind, kb, steps, nsteps, total, grid, st);
+    else launch_kind<T, OpMax>(kind, kb, steps, nsteps, total, grid, st);
+}
+
+void launch_worklist(int dtype, int op, int kind, int kb, const void* steps, int nsteps, i64 total,
+                     int grid, hipStream_t st) {
+    const Step* s = (const Step*)steps;
+    switch (dtype) {
+        case EXS_F32: launch_op<float>(op, kind, kb, s, nsteps, total, grid, st); break;
+        case EXS_F64: launch_op<double>(op, kind, kb, s, nsteps, total, grid, st); break;
+        case EXS_I32: launch_op<int>(op, kind, kb, s, nsteps, total, grid, st); break;
+        case EXS_I64: launch_op<long long>(op, kind, kb, s, nsteps, total, grid, st); break;
+    }
+}
+
+}  // namespace exs
