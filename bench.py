@@ -36,6 +36,13 @@ def parse():
     p.add_argument("--no-check", action="store_true")
     p.add_argument("--copy-probe", action="store_true",
                    help="also time a plain device copy of the input (bandwidth ceiling)")
+    p.add_argument("--no-batched", action="store_true", help="skip the batched form")
+    p.add_argument("--no-served", action="store_true", help="skip the serving form")
+    p.add_argument("--batch-count", type=int, default=512)
+    p.add_argument("--serve-seconds", type=float, default=4.0,
+                   help="window of the 2000 req/s Poisson stream that is served")
+    p.add_argument("--serve-budget-gib", type=float, default=32.0)
+    p.add_argument("--serve-inflight", type=int, default=8)
     return p.parse_args()
 
 
@@ -194,6 +201,11 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(a_host, w, N)
 
+    del outs, ws
+    torch.cuda.empty_cache()
+    batched = None if args.no_batched else bench_batched(args, P, _lib, torch, np)
+    served = None if args.no_served else bench_served(args, P, _lib, torch, np)
+
     line = {
         "metric": "excluded-sum Gelem/s + % HBM peak (d=3, 512^3 fp32); batched/served p50/p99",
         "value": round(value, 3),
@@ -217,8 +229,243 @@ def main():
         "cpu_baseline": cpu,
         "copy_probe": copy,
         "check": check,
+        "batched": batched,
+        "served": served,
     }
     print(json.dumps(line), flush=True)
+
+
+def _pct(v, p):
+    import math
+    v = sorted(v)
+    if not v:
+        return None
+    i = max(0, min(len(v) - 1, math.ceil(p * len(v)) - 1))
+    return v[i]
+
+
+def bench_batched(args, P, _lib, torch, np):
+    """Batched form: the 512-tensor mixed workload as one graph launch, vs
+    the same jobs as individual plain calls (exs_run per tensor, one stream)."""
+    from paper_2106_00124_amd import workloads as W
+    items = W.batch_workload(count=args.batch_count)
+    dev = torch.device("cuda:0")
+    L = _lib.lib()
+    stream = torch.cuda.current_stream()
+    xs = []
+    for it in items:
+        x = torch.empty(it.shape, dtype=torch.float32 if it.dtype == "f32" else torch.int32,
+                        device=dev)
+        if it.dtype == "f32":
+            P.fill(x, W.FILL_NORMALISH, it.seed)
+        else:
+            P.fill(x, W.FILL_UNIFORM_INT, it.seed, -100, 100)
+        xs.append(x)
+    total = sum(it.n for it in items)
+    log(f"batched: {len(items)} tensors, {total / 1e6:.1f} M elements")
+    cache = os.environ.get("EXSUM_TUNE_CACHE",
+                           os.path.join(os.path.expanduser("~"), ".cache", "exsum_tune.json"))
+    t0 = time.perf_counter()
+    B = P.Batch([(x, it.box, it.op, "both") for x, it in zip(xs, items)], tune_cache=cache)
+    build_s = time.perf_counter() - t0
+    info = B.info()
+
+    def timed(fn, reps):
+        evs = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        return [a.elapsed_time(b) for a, b in evs]
+
+    for _ in range(3):
+        B.launch(stream)
+    torch.cuda.synchronize()
+    reps = max(args.steps, 5)
+    g = timed(lambda: B.launch(stream), reps)
+    e = timed(lambda: B.launch_eager(stream), reps)
+    graph_out = [(i.clone(), x.clone()) for i, x in B.outputs]
+
+    # per-tensor plain calls with prebuilt jobs and one shared workspace
+    jobs, outs = [], []
+    wsz = 0
+    for x, it in zip(xs, items):
+        inc, exc = torch.empty_like(x), torch.empty_like(x)
+        j = P.job_for(x, it.box, it.op, "both", inc, exc)
+        n = ctypes.c_size_t()
+        _lib.check(L.exs_workspace_size(ctypes.byref(j), ctypes.byref(n)))
+        wsz = max(wsz, n.value)
+        jobs.append(j)
+        outs.append((inc, exc))
+    ws = torch.empty(max(wsz, 1), dtype=torch.uint8, device=dev)
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    wp = ctypes.c_void_p(ws.data_ptr())
+
+    def per_tensor():
+        for j in jobs:
+            rc = L.exs_run(ctypes.byref(j), wp, ws.numel(), sp)
+            if rc:
+                _lib.check(rc)
+
+    per_tensor()
+    torch.cuda.synchronize()
+    pt = timed(per_tensor, max(3, reps // 2))
+    # agreement between the graph launch and the plain calls
+    exact = close = 0
+    worst = 0.0
+    for (gi, ge), (pi, pe), it in zip(graph_out, outs, items):
+        for a, b in ((gi, pi), (ge, pe)):
+            if it.dtype == "i32" or it.op == "max":
+                exact += int(torch.equal(a, b))
+            else:
+                d = ((a - b).abs().max() / b.abs().max().clamp_min(1e-30)).item()
+                worst = max(worst, d)
+                close += int(d <= 1e-5)
+    n_exact = sum(2 for it in items if it.dtype == "i32" or it.op == "max")
+    ms_g = _pct(g, 0.5)
+    res = {
+        "jobs": len(items), "elements": int(total), "outputs": ["included", "excluded"],
+        "graph_ms_p50": round(ms_g, 4), "graph_ms_p99": round(_pct(g, 0.99), 4),
+        "eager_ms_p50": round(_pct(e, 0.5), 4),
+        "per_tensor_ms_p50": round(_pct(pt, 0.5), 4),
+        "gelem_per_s": round(total / (ms_g * 1e-3) / 1e9, 2),
+        "per_tensor_gelem_per_s": round(total / (_pct(pt, 0.5) * 1e-3) / 1e9, 2),
+        "speedup_vs_per_tensor": round(_pct(pt, 0.5) / ms_g, 3),
+        "graph_nodes": info["graph_nodes"], "work_items": info["work_items"],
+        "build_s": round(build_s, 2),
+        "agree_with_plain": {"bit_exact": f"{exact}/{n_exact}",
+                             "f32_sum_within_1e-5": f"{close}/{2 * len(items) - n_exact}",
+                             "f32_sum_worst_rel": worst},
+        "values": "device counter fill: f32 normalish (sum of four uniforms), i32 uniform "
+                  "[-100,100]",
+    }
+    log(f"batched: graph {ms_g:.3f} ms, eager {res['eager_ms_p50']:.3f} ms, "
+        f"per-tensor {res['per_tensor_ms_p50']:.3f} ms")
+    B.close()
+    return res
+
+
+def bench_served(args, P, _lib, torch, np):
+    """Serving form: a window of the Poisson request stream (excluded sums,
+    inputs generated on the device) through the server, vs the serial plain
+    path (one request at a time on one stream) on the same arrivals."""
+    from paper_2106_00124_amd import workloads as W
+    reqs = W.serving_workload(duration_s=args.serve_seconds)
+    elems = sum(r.n for r in reqs)
+    log(f"served: {len(reqs)} requests in {args.serve_seconds:.1f}s, "
+        f"{elems / 1e9:.2f} G elements")
+    S = P.Server(hbm_budget=int(args.serve_budget_gib * (1 << 30)),
+                 max_inflight=args.serve_inflight)
+    # warm the kernels of both operators and the generic/fused paths
+    for r in reqs[:16]:
+        S.submit_generated(r.shape, r.box, torch.float32, r.op, "exc", kind=W.FILL_LOGMAG,
+                           seed=r.fill_seed)
+    S.drain()
+    S.close()
+
+    def open_loop(S):
+        from collections import deque
+        pend = deque()
+        late = []
+        t0 = time.perf_counter()
+        for r in reqs:
+            while True:
+                now = time.perf_counter() - t0
+                while pend and S.done(pend[0]):
+                    S.release(pend.popleft())
+                if now >= r.arrival_s:
+                    break
+                if r.arrival_s - now > 3e-4:
+                    time.sleep(1e-4)
+            late.append(time.perf_counter() - t0 - r.arrival_s)
+            pend.append(S.submit_generated(r.shape, r.box, torch.float32, r.op, "exc",
+                                           kind=W.FILL_LOGMAG, seed=r.fill_seed))
+        while pend:
+            if S.done(pend[0]):
+                S.release(pend.popleft())
+        wall = time.perf_counter() - t0
+        return late, wall
+
+    S = P.Server(hbm_budget=int(args.serve_budget_gib * (1 << 30)),
+                 max_inflight=args.serve_inflight)
+    late, wall = open_loop(S)
+    st = S.stats()
+    S.close()
+    log(f"served: p50 {st['p50_ms']:.3f} ms p99 {st['p99_ms']:.3f} ms, {st['req_per_s']:.0f} req/s")
+
+    # saturated: every request submitted at once (throughput)
+    S = P.Server(hbm_budget=int(args.serve_budget_gib * (1 << 30)),
+                 max_inflight=args.serve_inflight)
+    from collections import deque
+    pend = deque()
+    t0 = time.perf_counter()
+    for r in reqs:
+        pend.append(S.submit_generated(r.shape, r.box, torch.float32, r.op, "exc",
+                                       kind=W.FILL_LOGMAG, seed=r.fill_seed))
+        while pend and S.done(pend[0]):
+            S.release(pend.popleft())
+    while pend:
+        if S.done(pend[0]):
+            S.release(pend.popleft())
+    sat_s = time.perf_counter() - t0
+    S.close()
+
+    # serial plain path on one stream, same arrivals
+    L = _lib.lib()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    maxn = max(r.n for r in reqs)
+    wsz = 0
+    for r in reqs:
+        wsz = max(wsz, P.workspace_size(r.shape, r.box, torch.float32, r.op, "exc"))
+    xin = torch.empty(maxn, dtype=torch.float32, device=dev)
+    xout = torch.empty(maxn, dtype=torch.float32, device=dev)
+    ws = torch.empty(max(wsz, 1), dtype=torch.uint8, device=dev)
+    sp = ctypes.c_void_p(stream.cuda_stream)
+
+    def serial_one(r):
+        _lib.check(L.exs_fill(ctypes.c_void_p(xin.data_ptr()), r.n, _lib.F32, W.FILL_LOGMAG,
+                              ctypes.c_uint64(r.fill_seed), -100, 100, sp))
+        j = _lib.make_job(len(r.shape), _lib.F32, _lib.SUM if r.op == "sum" else _lib.MAX,
+                          _lib.EXCLUDED, list(r.shape), list(r.box), xin.data_ptr(), None,
+                          xout.data_ptr())
+        _lib.check(L.exs_run(ctypes.byref(j), ctypes.c_void_p(ws.data_ptr()), ws.numel(), sp))
+
+    lat = []
+    t0 = time.perf_counter()
+    for r in reqs:
+        while time.perf_counter() - t0 < r.arrival_s:
+            pass
+        serial_one(r)
+        stream.synchronize()
+        lat.append((time.perf_counter() - t0 - r.arrival_s) * 1e3)
+    t1 = time.perf_counter()
+    for r in reqs:
+        serial_one(r)
+    stream.synchronize()
+    serial_sat = time.perf_counter() - t1
+    res = {
+        "requests": len(reqs), "window_s": args.serve_seconds, "rate_per_s": 2000,
+        "elements": int(elems), "outputs": ["excluded"], "hbm_budget_gib": args.serve_budget_gib,
+        "max_inflight": args.serve_inflight,
+        "p50_ms": round(st["p50_ms"], 4), "p99_ms": round(st["p99_ms"], 4),
+        "req_per_s": round(st["req_per_s"], 1), "gelem_per_s": round(st["gelem_per_s"], 3),
+        "max_queue": st["max_queue"], "peak_bytes": st["peak_bytes"],
+        "submit_lateness_p99_ms": round(_pct(late, 0.99) * 1e3, 4),
+        "saturated_req_per_s": round(len(reqs) / sat_s, 1),
+        "saturated_gelem_per_s": round(elems / sat_s / 1e9, 3),
+        "serial_p50_ms": round(_pct(lat, 0.5), 4), "serial_p99_ms": round(_pct(lat, 0.99), 4),
+        "serial_saturated_req_per_s": round(len(reqs) / serial_sat, 1),
+        "serial_saturated_gelem_per_s": round(elems / serial_sat / 1e9, 3),
+        "latency": "submit to completion seen by the server (serial: arrival to stream sync)",
+    }
+    log(f"serial: p50 {res['serial_p50_ms']:.3f} ms p99 {res['serial_p99_ms']:.3f} ms; "
+        f"saturated {res['saturated_req_per_s']:.0f} vs {res['serial_saturated_req_per_s']:.0f} req/s")
+    return res
 
 
 def spot_check(a_host, w, outs, np):

@@ -174,18 +174,36 @@ typedef struct exs_server exs_server;
  * arrival order while their bytes fit the free budget and a stream slot is
  * free; admitted work overlaps on the device. */
 exs_status exs_server_create(size_t hbm_budget, int32_t max_inflight, exs_server **out);
-/* Queue a request.  job->in_dev must stay valid until the ticket completes;
- * job->mode selects outputs; output pointers in the job are ignored (the
- * server allocates them).  Never blocks; fails only for an invalid job or one
- * larger than the whole budget (EXS_ENOMEM). */
+/* Queue a request.  job->in_dev (caller-owned) must stay valid and
+ * unchanged until the ticket completes; job->mode selects outputs; output
+ * pointers in the job are ignored (the server allocates them in its arena).
+ * Never blocks; fails only for an invalid job (EXS_EINVAL) or one larger
+ * than the whole budget (EXS_ENOMEM).  A request that does not fit the free
+ * arena waits in the queue, and so do the requests behind it.  The work
+ * computes what exs_run computes for the same job. */
 exs_status exs_server_submit(exs_server *s, const exs_job *job, uint64_t *ticket);
-/* EXS_OK and the device pointers of the outputs once the request completed,
- * EXS_ENOTREADY before.  Pointers stay valid until release. */
+/* The same, but the server builds the input tensor itself inside its arena
+ * (exs_fill with fill_kind/seed/lo/hi, enqueued on the request's stream just
+ * before its work), so request tensors are produced and kept on the device.
+ * job->in_dev is ignored; fill kind 1 needs an integer dtype, kinds 0 and 2
+ * need EXS_F32 (EXS_EINVAL otherwise). */
+exs_status exs_server_submit_generated(exs_server *s, const exs_job *job, int32_t fill_kind,
+                                       uint64_t seed, int64_t lo, int64_t hi, uint64_t *ticket);
+/* EXS_OK and the device pointers of the outputs (row-major, the job's dims
+ * and dtype; NULL for an output not requested) once the request completed,
+ * EXS_ENOTREADY before, EXS_EDEVICE if its launch failed, EXS_ENOTFOUND for
+ * an unknown or released ticket.  Pointers stay valid until release. */
 exs_status exs_server_poll(exs_server *s, uint64_t ticket, const void **inc_dev,
                            const void **exc_dev, double *latency_ms);
-/* Block until every submitted request has completed. */
+/* Device pointer of a completed request's input (its generated tensor for
+ * exs_server_submit_generated); valid until release. */
+exs_status exs_server_input(exs_server *s, uint64_t ticket, const void **in_dev);
+/* Block until every submitted request has completed.  EXS_EAGAIN when no
+ * request runs and the queue head cannot fit because completed requests
+ * still hold the arena (release them, then drain again). */
 exs_status exs_server_drain(exs_server *s);
-/* Return a completed request's memory to the arena. */
+/* Return a completed (or failed) request's memory to the arena and forget
+ * its ticket; EXS_ENOTREADY while it is queued or running. */
 exs_status exs_server_release(exs_server *s, uint64_t ticket);
 /* Latency percentiles (submit -> completion event) and throughput over the
  * completed requests so far; queue depth and peak in-flight bytes. */

@@ -168,3 +168,123 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+_TYPESTR = {_lib.F32: "<f4", _lib.F64: "<f8", _lib.I32: "<i4", _lib.I64: "<i8"}
+
+
+class _DeviceView:
+    """A raw device buffer exposed through the CUDA array interface, so that
+    torch can wrap it without a copy."""
+
+    def __init__(self, ptr, shape, dtype_code):
+        self.__cuda_array_interface__ = {"shape": tuple(int(v) for v in shape),
+                                         "typestr": _TYPESTR[dtype_code],
+                                         "data": (int(ptr), False), "version": 2,
+                                         "strides": None}
+
+
+class Server:
+    """Serving form (see exs_server_* in exsum.h): requests are admitted in
+    arrival order while their outputs and workspace fit ``hbm_budget`` bytes
+    and one of ``max_inflight`` streams is idle; admitted requests run
+    concurrently.
+
+    ``submit`` returns a ticket; ``result`` returns ``(inc, exc)`` as torch
+    views of the server's arena once the request completed (None before).
+    The views are valid until ``release``; clone them to keep them longer.
+    """
+
+    def __init__(self, hbm_budget, max_inflight=4):
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().exs_server_create(int(hbm_budget), int(max_inflight),
+                                                ctypes.byref(h)))
+        self._h = h
+        self._meta = {}
+        self._keep = {}
+
+    def submit(self, x, box, op="sum", mode="both"):
+        if not x.is_cuda or not x.is_contiguous():
+            raise ExsError(1, "server inputs must be contiguous device tensors")
+        j = job_for(x, box, op, mode)
+        t = ctypes.c_uint64()
+        _lib.check(_lib.lib().exs_server_submit(self._h, ctypes.byref(j), ctypes.byref(t)))
+        self._meta[t.value] = (tuple(x.shape), j.dtype)
+        self._keep[t.value] = x
+        return t.value
+
+    def submit_generated(self, shape, box, dtype, op="sum", mode="both", kind=0, seed=0,
+                         lo=-100, hi=100):
+        """Queue a request whose input the server fills itself (exs_fill)."""
+        code = _dtype_code(dtype)
+        j = _lib.make_job(len(shape), code, _OPS[op], _mode_code(mode), list(shape),
+                          [int(v) for v in box], None, None, None)
+        t = ctypes.c_uint64()
+        _lib.check(_lib.lib().exs_server_submit_generated(
+            self._h, ctypes.byref(j), int(kind), ctypes.c_uint64(seed), int(lo), int(hi),
+            ctypes.byref(t)))
+        self._meta[t.value] = (tuple(int(v) for v in shape), code)
+        return t.value
+
+    def _view(self, ptr, ticket):
+        import torch
+        if not ptr:
+            return None
+        shape, code = self._meta[ticket]
+        return torch.as_tensor(_DeviceView(ptr, shape, code), device="cuda")
+
+    def result(self, ticket):
+        inc = ctypes.c_void_p()
+        exc = ctypes.c_void_p()
+        lat = ctypes.c_double()
+        rc = _lib.lib().exs_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(inc),
+                                        ctypes.byref(exc), ctypes.byref(lat))
+        if rc == _lib.ENOTREADY:
+            return None
+        _lib.check(rc)
+        return self._view(inc.value, ticket), self._view(exc.value, ticket), lat.value
+
+    def done(self, ticket):
+        """True once the request completed (no views are built)."""
+        rc = _lib.lib().exs_server_poll(self._h, ctypes.c_uint64(ticket), None, None, None)
+        if rc == _lib.ENOTREADY:
+            return False
+        _lib.check(rc)
+        return True
+
+    def input(self, ticket):
+        p = ctypes.c_void_p()
+        rc = _lib.lib().exs_server_input(self._h, ctypes.c_uint64(ticket), ctypes.byref(p))
+        if rc == _lib.ENOTREADY:
+            return None
+        _lib.check(rc)
+        return self._view(p.value, ticket)
+
+    def drain(self):
+        _lib.check(_lib.lib().exs_server_drain(self._h))
+
+    def release(self, ticket):
+        _lib.check(_lib.lib().exs_server_release(self._h, ctypes.c_uint64(ticket)))
+        self._meta.pop(ticket, None)
+        self._keep.pop(ticket, None)
+
+    def stats(self):
+        d = [ctypes.c_double() for _ in range(4)]
+        i = [ctypes.c_int64() for _ in range(3)]
+        _lib.check(_lib.lib().exs_server_stats(self._h, *[ctypes.byref(v) for v in d],
+                                               *[ctypes.byref(v) for v in i]))
+        return {"p50_ms": d[0].value, "p99_ms": d[1].value, "req_per_s": d[2].value,
+                "gelem_per_s": d[3].value, "completed": i[0].value,
+                "max_queue": i[1].value, "peak_bytes": i[2].value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().exs_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

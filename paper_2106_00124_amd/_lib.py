@@ -16,6 +16,7 @@ MAX_RANK = 8
 F32, F64, I32, I64 = 0, 1, 2, 3
 SUM, MAX = 0, 1
 INCLUDED, EXCLUDED = 1, 2
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE, EAGAIN, ENOTREADY, ENOTFOUND = range(8)
 
 STATUS = {0: "EXS_OK", 1: "EXS_EINVAL", 2: "EXS_EUNSUPPORTED", 3: "EXS_ENOMEM",
           4: "EXS_EDEVICE", 5: "EXS_EAGAIN", 6: "EXS_ENOTREADY", 7: "EXS_ENOTFOUND"}
@@ -67,6 +68,10 @@ SIGNATURES = {
     "exs_batch_destroy": (None, [_P]),
     "exs_server_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(_P)]),
     "exs_server_submit": (ctypes.c_int, [_P, _JP, ctypes.POINTER(ctypes.c_uint64)]),
+    "exs_server_submit_generated": (ctypes.c_int, [_P, _JP, ctypes.c_int32, ctypes.c_uint64,
+                                                   ctypes.c_int64, ctypes.c_int64,
+                                                   ctypes.POINTER(ctypes.c_uint64)]),
+    "exs_server_input": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(_P)]),
     "exs_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(_P),
                                        ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_double)]),
     "exs_server_drain": (ctypes.c_int, [_P]),
