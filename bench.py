@@ -268,7 +268,6 @@ def bench_batched(args, P, _lib, torch, np):
     t0 = time.perf_counter()
     B = P.Batch([(x, it.box, it.op, "both") for x, it in zip(xs, items)], tune_cache=cache)
     build_s = time.perf_counter() - t0
-    info = B.info()
 
     def timed(fn, reps):
         evs = []
@@ -287,6 +286,7 @@ def bench_batched(args, P, _lib, torch, np):
     torch.cuda.synchronize()
     reps = max(args.steps, 5)
     g = timed(lambda: B.launch(stream), reps)
+    info = B.info()
     e = timed(lambda: B.launch_eager(stream), reps)
     graph_out = [(i.clone(), x.clone()) for i, x in B.outputs]
 
