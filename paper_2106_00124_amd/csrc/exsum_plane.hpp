@@ -107,7 +107,10 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, 
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, 0, 0);
 }
 
-template <typename T, class Op, int K0B, int KP>
+// WHOLE: every block of the run is exactly K0B planes (k0 == K0B, n0 a
+// multiple of k0) and K0B / P is even, so each block is a fixed sequence of
+// full rounds; otherwise rounds are sized at run time.
+template <typename T, class Op, int K0B, int KP, bool WHOLE>
 __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
     using C = PlaneCfg<KP>;
     constexpr int NT = C::NT, P = C::P, SA = C::SA, SB = C::SB;
@@ -130,8 +133,14 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
     const int seg = (int)(rest / a.MID);
     const int k0 = a.k0, ky = a.ky, kx = a.kx;
     const int NY = (int)a.NY, NX = (int)a.NX;
-    const int y0 = (int)(tile / a.tilesX) * (C::NBY * ky);
-    const int x0 = (int)(tile % a.tilesX) * (C::NBX * kx);
+    // tiles in groups of four tile rows, column by column inside a group, so
+    // that one XCD's run of tiles is a compact patch of the plane (its halos
+    // are mostly read by the same L2)
+    const i64 grow = 4 * a.tilesX;
+    const i64 g0 = tile / grow, gin = tile % grow;
+    const i64 gh = a.tilesY - g0 * 4 < 4 ? a.tilesY - g0 * 4 : 4;
+    const int y0 = (int)(g0 * 4 + gin % gh) * (C::NBY * ky);
+    const int x0 = (int)(gin / gh) * (C::NBX * kx);
     // plane and block indices fit in 32 bits (checked by the planner)
     const int Qn = (int)a.Q;
     const int qa = seg * (int)a.segblocks;
@@ -198,18 +207,23 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
     T* __restrict__ exc = (T*)a.exc;
     T* __restrict__ inc = (T*)a.inc;
 
-    Axis0State<T, Op, K0B> st;
-    st.P = e;
+    // axis-0 state: the box-summed values of the last complete block (raw;
+    // its range prefixes and suffixes are formed when it is emitted) and the
+    // op of everything before that block (with the lower-dimensional term)
+    T w[K0B];
+#pragma unroll
+    for (int r = 0; r < K0B; ++r) w[r] = e;
+    T Pb = e;
     if (do_ex) {
-        st.P = bload<T>(buf((const T*)a.PX + (i64)qa * M, plane_bytes), mb);
-        if (a.Trest) st.P = Op::apply(st.P, bload<T>(buf(a.Trest, plane_bytes), mb));
+        Pb = bload<T>(buf((const T*)a.PX + (i64)qa * M, plane_bytes), mb);
+        if (a.Trest) Pb = Op::apply(Pb, bload<T>(buf(a.Trest, plane_bytes), mb));
     }
     // SX of the block being filled: loaded when the block starts, from an
     // in-range block index; the identity past the last block is applied at use
     T sx_raw = e;
     bool sx_valid = false;
 
-    // Emit block (q-1) from the ring holding block q, then absorb block q.
+    // Emit block (q-1) from w and the ring holding block q, then keep block q.
     // Ring slots past k0, and past the end of the tensor, hold the identity;
     // rows of block q-1 past the tensor end fall outside the store range.
     auto block_step = [&](int q) __attribute__((always_inline)) {
@@ -221,62 +235,79 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
             const int xb = (q - 1) * k0;
             const int nrows = n0 - xb < k0 ? n0 - xb : k0;
             const unsigned blk_bytes = (unsigned)nrows * plane_bytes;
+            T tmp[K0B];
             if (do_ex) {
+                // prefix before each row of block q-1, then the suffix from
+                // the same row of block q on
+#pragma unroll
+                for (int r = 0; r < K0B; ++r) { tmp[r] = Pb; Pb = Op::apply(Pb, w[r]); }
                 const __amdgpu_buffer_rsrc_t ob = buf(exc + (i64)xb * M, blk_bytes);
                 T S = sx_valid ? sx_raw : e;
 #pragma unroll
                 for (int r = K0B - 1; r >= 0; --r) {
                     S = Op::apply(v[r], S);
-                    bstore<T>(ob, mb + (unsigned)r * plane_bytes, Op::apply(st.pex[r], S));
+                    bstore<T>(ob, mb + (unsigned)r * plane_bytes, Op::apply(tmp[r], S));
                 }
             }
             if (do_inc) {
+                // BDBS along axis 0: range suffix in block q-1, range prefix
+                // of block q up to the row before
+                T s = e;
+#pragma unroll
+                for (int r = K0B - 1; r >= 0; --r) { s = Op::apply(w[r], s); tmp[r] = s; }
                 const __amdgpu_buffer_rsrc_t ob = buf(inc + (i64)xb * M, blk_bytes);
                 T p = e;
 #pragma unroll
                 for (int r = 0; r < K0B; ++r) {
-                    T val = st.rs[r];
+                    T val = tmp[r];
                     if (r > 0) { p = Op::apply(p, v[r - 1]); val = Op::apply(val, p); }
                     bstore<T>(ob, mb + (unsigned)r * plane_bytes, val);
                 }
             }
         }
-        if (q < qb) st.absorb_all(v);
+        if (q < qb) {
+#pragma unroll
+            for (int r = 0; r < K0B; ++r) w[r] = v[r];
+        }
     };
     auto ring_fill_identity = [&](int from) {
         for (int r = from; r < K0B; ++r) ring[r * NT + tid] = e;
     };
 
-    // raw prefetched halo values (consumed only when staged into LDS)
-    T pre[P][C::NLOAD];
-    auto fetch_round = [&](int t, int np) __attribute__((always_inline)) {
-#pragma unroll
-        for (int u = 0; u < P; ++u) {
-            const __amdgpu_buffer_rsrc_t pl = buf(X + (i64)(u < np ? t + u : t) * M, plane_bytes);
-#pragma unroll
-            for (int j = 0; j < C::NLOAD; ++j) pre[u][j] = bload<T>(pl, goff[j]);
-        }
-    };
     auto round_len = [&](int tt, int rr) -> int {
         int n = k0 - rr;
         if (tt + n > t_end) n = t_end - tt;
         return n < P ? n : P;
     };
+    // Rounds of up to P planes that stay inside one k0-block.  Raw halo
+    // values are prefetched two rounds ahead into two register sets used
+    // alternately (consumed only when staged into LDS).
+    int tf = t_begin, rf = 0;  // the next round to fetch
+    // The loads are issued unconditionally (past the run they re-read its
+    // first plane), so the number of loads between a load and its use is the
+    // same on every path and the compiler's waits stay exact.
+    auto fetch_next = [&](T (&pre)[P][C::NLOAD]) __attribute__((always_inline)) {
+        const bool live = tf < t_end;
+        const int np = live ? round_len(tf, rf) : P;
+        const int tb = live ? tf : t_begin;
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            const __amdgpu_buffer_rsrc_t pl = buf(X + (i64)(u < np ? tb + u : tb) * M, plane_bytes);
+#pragma unroll
+            for (int j = 0; j < C::NLOAD; ++j) pre[u][j] = bload<T>(pl, goff[j]);
+        }
+        if (live) {
+            tf += np;
+            rf = rf + np == k0 ? 0 : rf + np;
+        }
+    };
 
-    // rounds of up to P planes that stay inside one k0-block
     int qlast = qa - 1;
     int t = t_begin, q = qa, r0 = 0;
-    int np = t < t_end ? round_len(t, 0) : 0;
-    if (np > 0) fetch_round(t, np);
-    __syncthreads();  // identity fill visible before the first staging
-    while (t < t_end) {
-        if (r0 == 0) {
-            sx_valid = q < Qn;
-            if (do_ex)
-                sx_raw = bload<T>(buf((const T*)a.SX + (i64)(q < Qn ? q : Qn - 1) * M, plane_bytes),
-                                  mb);
-        }
-        // 1. stage this round's halo tiles; start loading the next round
+    // one round: NP planes (NP = P for whole blocks, else run-time np)
+    auto round = [&](T (&pre)[P][C::NLOAD], int np) __attribute__((always_inline)) {
+        // 1. stage this round's halo tiles; refill the register set two
+        //    rounds ahead
 #pragma unroll
         for (int u = 0; u < P; ++u) {
             if (u < np) {
@@ -287,10 +318,7 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
                 }
             }
         }
-        const int tn = t + np;
-        const int rn = r0 + np == k0 ? 0 : r0 + np;
-        const int npn = tn < t_end ? round_len(tn, rn) : 0;
-        if (npn > 0) fetch_round(tn, npn);
+        fetch_next(pre);
         __syncthreads();
         // 2. BDBS along x for every blocked halo row of every plane of the round
 #pragma unroll
@@ -313,16 +341,56 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
                                                       ring + (r0 + u) * NT + b * KP * C::TXM + col);
             }
         }
-        // 4. a block of W planes is complete: emit the previous block
-        if (r0 + np == k0 || tn == n0) {
-            if (r0 + np < k0) ring_fill_identity(r0 + np);  // the tensor ends inside the block
+    };
+    auto load_sx = [&]() __attribute__((always_inline)) {
+        sx_valid = q < Qn;
+        if (do_ex)
+            sx_raw = bload<T>(buf((const T*)a.SX + (i64)(q < Qn ? q : Qn - 1) * M, plane_bytes), mb);
+    };
+
+    T pre0[P][C::NLOAD], pre1[P][C::NLOAD];
+    fetch_next(pre0);
+    fetch_next(pre1);
+    __syncthreads();  // identity fill visible before the first staging
+    if constexpr (WHOLE) {
+        static_assert(K0B % (2 * P) == 0, "whole blocks take an even number of rounds");
+        // blocks qa .. of the run, K0B / P full rounds each
+        for (; t < t_end; ++q) {
+            load_sx();
+#pragma unroll
+            for (int rr = 0; rr < K0B / P; rr += 2) {
+                r0 = rr * P;
+                round(pre0, P);
+                r0 = (rr + 1) * P;
+                round(pre1, P);
+            }
+            r0 = 0;
+            t += K0B;
             block_step(q);
             qlast = q;
         }
-        t = tn;
-        if (rn == 0) ++q;
-        r0 = rn;
-        np = npn;
+    } else {
+        auto step = [&](T (&pre)[P][C::NLOAD]) __attribute__((always_inline)) {
+            const int np = round_len(t, r0);
+            if (r0 == 0) load_sx();
+            round(pre, np);
+            // 4. a block of W planes is complete: emit the previous block
+            const int tn = t + np;
+            const int rn = r0 + np == k0 ? 0 : r0 + np;
+            if (r0 + np == k0 || tn == n0) {
+                if (r0 + np < k0) ring_fill_identity(r0 + np);  // the tensor ends inside the block
+                block_step(q);
+                qlast = q;
+            }
+            t = tn;
+            if (rn == 0) ++q;
+            r0 = rn;
+        };
+        while (t < t_end) {
+            step(pre0);
+            if (t >= t_end) break;
+            step(pre1);
+        }
     }
     // the block after the run lies past the tensor: emit the last block
     if (qlast < qb) {
@@ -495,8 +563,16 @@ void launch_plane_kernel(PlaneArgs pa, hipStream_t st) {
     pa.segblocks = (pa.Q + nseg - 1) / nseg;
     pa.nseg = (pa.Q + pa.segblocks - 1) / pa.segblocks;
     const i64 grid = tiles * pa.nseg;
-    hipLaunchKernelGGL((k_plane_axis0<T, Op, K0B, KP>), dim3((unsigned)grid), dim3(C::NT), 0, st,
-                       pa);
+    // whole blocks: every block of every run has exactly K0B planes
+    if constexpr (K0B % (2 * C::P) == 0) {
+        if (pa.k0 == K0B && pa.n0 % K0B == 0) {
+            hipLaunchKernelGGL((k_plane_axis0<T, Op, K0B, KP, true>), dim3((unsigned)grid),
+                               dim3(C::NT), 0, st, pa);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_plane_axis0<T, Op, K0B, KP, false>), dim3((unsigned)grid), dim3(C::NT),
+                       0, st, pa);
 }
 
 template <typename T, class Op, int K0B>
