@@ -102,7 +102,7 @@ def profiled_traffic(kernel, workload):
     vals = {}
     with open(path) as fh:
         for line in fh:
-            line = line.strip().strip("`")
+            line = line.strip().lstrip("-* ").strip("`")
             if ":" in line:
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
