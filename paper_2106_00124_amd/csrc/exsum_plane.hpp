@@ -106,6 +106,14 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, 
     static_assert(sizeof(T) == 4, "4-byte elements");
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, 0, 0);
 }
+// The same with the non-temporal hint (cache-policy bit NT): for the output
+// planes, which nothing reads again, so that they do not evict from L2 the
+// input rows that neighbouring tiles still read as halo.
+template <typename T>
+__device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, unsigned voff, T v) {
+    static_assert(sizeof(T) == 4, "4-byte elements");
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, 0, 2);
+}
 
 // WHOLE: every block of the run is exactly K0B planes (k0 == K0B, n0 a
 // multiple of k0) and K0B / P is even, so each block is a fixed sequence of
@@ -246,7 +254,7 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
 #pragma unroll
                 for (int r = K0B - 1; r >= 0; --r) {
                     S = Op::apply(v[r], S);
-                    bstore<T>(ob, mb + (unsigned)r * plane_bytes, Op::apply(tmp[r], S));
+                    bstore_nt<T>(ob, mb + (unsigned)r * plane_bytes, Op::apply(tmp[r], S));
                 }
             }
             if (do_inc) {
@@ -261,7 +269,7 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
                 for (int r = 0; r < K0B; ++r) {
                     T val = tmp[r];
                     if (r > 0) { p = Op::apply(p, v[r - 1]); val = Op::apply(val, p); }
-                    bstore<T>(ob, mb + (unsigned)r * plane_bytes, val);
+                    bstore_nt<T>(ob, mb + (unsigned)r * plane_bytes, val);
                 }
             }
         }
