@@ -155,6 +155,11 @@ struct EagerSink {
             launch_plane_axis0<T, Op>(X, PX, SX, Trest, exc, inc, n0, MID, NY, NX, k0, ky, kx, Q,
                                       st);
     }
+    void plane_scan(const T* G, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 MID, i64 NY, i64 NX,
+                    i64 ky, i64 kx, i64 pxe) {
+        if constexpr (sizeof(T) == 4)
+            launch_plane_scan<T, Op>(G, Ga, PX, SX, R, Q, MID, NY, NX, ky, kx, pxe, st);
+    }
     void plane_bdbs(const T* X, T* W, i64 O, i64 NY, i64 NX, i64 ky, i64 kx) {
         if constexpr (sizeof(T) == 4) launch_plane_bdbs<T, Op>(X, W, O, NY, NX, ky, kx, st);
     }

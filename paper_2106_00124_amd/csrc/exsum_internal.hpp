@@ -49,6 +49,12 @@ bool plane_eligible(int d, const i64* n, const i64* k, int es);
 template <typename T, class Op>
 void launch_plane_bdbs(const T* X, T* W, i64 O, i64 NY, i64 NX, i64 ky, i64 kx, hipStream_t st);
 bool plane2_eligible(i64 NY, i64 NX, i64 ky, i64 kx, int es);
+template <typename T, class Op>
+void launch_plane_scan(const T* G, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 MID, i64 NY,
+                       i64 NX, i64 ky, i64 kx, i64 pxe, hipStream_t st);
+// blocks of axis 0 per run of the level-0 streaming kernel (the runs start
+// at multiples of it: the only blocks whose prefix it reads)
+i64 plane_axis0_run_blocks(i64 Q, i64 MID, i64 NY, i64 NX, i64 ky, i64 kx);
 void launch_fill(void* out, i64 count, int dtype, int kind, uint64_t seed, i64 lo, i64 hi,
                  float scale, hipStream_t st);
 

@@ -149,8 +149,21 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
         gk[0] = 1;
         for (int a = 1; a < dj; ++a) { gn[a] = n[j + a]; gk[a] = k[j + a]; }
         const T* Gw;
-        if (j == 0 && fused && plane2_eligible(n[d - 2], n[d - 1], k[d - 2], k[d - 1],
-                                               (int)sizeof(T))) {
+        const bool p2 = j == 0 && fused &&
+                        plane2_eligible(n[d - 2], n[d - 1], k[d - 2], k[d - 1], (int)sizeof(T));
+        if (p2 && Q[0] <= 32) {
+            // middle axes by the generic passes; the two trailing axes and the
+            // block scans in one pass (the box-summed planes are not stored)
+            const T* G1 = filter_axes<T>(Ga, gn, gk, dj, 1, dj - 3, gb0, gb1, dry, sink);
+            // the streaming kernel reads the block prefix only where its runs start
+            if (!dry)
+                sink.plane_scan(G1, Ga, PX[0], SX[0], R[1], Q[0], prod(n, 1, d - 2), n[d - 2],
+                                n[d - 1], k[d - 2], k[d - 1],
+                                plane_axis0_run_blocks(Q[0], prod(n, 1, d - 2), n[d - 2],
+                                                       n[d - 1], k[d - 2], k[d - 1]));
+            continue;
+        }
+        if (p2) {
             // middle axes by the generic passes, the two trailing axes in one
             // LDS-tiled pass
             const T* G1 = filter_axes<T>(Ga, gn, gk, dj, 1, dj - 3, gb0, gb1, dry, sink);

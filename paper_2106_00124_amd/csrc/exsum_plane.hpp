@@ -62,6 +62,23 @@ struct PlaneCfg {
     static constexpr int CT = (P * TXM * NBY + NT - 1) / NT;   // column tasks per thread
 };
 
+// Blocks of axis 0 per workgroup run of the streaming kernel: enough runs
+// that the workgroups cover every CU (each run reads one extra block).
+inline i64 plane_run_blocks(i64 Q, i64 tiles) {
+    i64 nseg = (256 + tiles - 1) / tiles;
+    if (nseg > Q) nseg = Q;
+    if (nseg < 1) nseg = 1;
+    return (Q + nseg - 1) / nseg;
+}
+
+// Tiles of the (NY, NX) plane for boxes (ky, kx) (the KP bucket's tile shape).
+inline i64 plane_tiles(i64 NY, i64 NX, i64 ky, i64 kx) {
+    const i64 km = ky > kx ? ky : kx;
+    const i64 kp = km <= 2 ? 2 : km <= 4 ? 4 : km <= 8 ? 8 : 16;
+    const i64 ty = (32 / kp) * ky, tx = (32 / kp) * kx;
+    return ((NY + ty - 1) / ty) * ((NX + tx - 1) / tx);
+}
+
 // One BDBS block over KP slots: out[r] = rsuf_b[r] op rpre_{b+1}[r-1]
 // (out[0] = rsuf_b[0]); src[0..KP) is the block, src[KP..2KP-1) the next one,
 // strided by SS in LDS.  Loads issue back to back; no branches.
@@ -528,6 +545,214 @@ __global__ void __launch_bounds__(1024) k_plane_bdbs(Plane2Args a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Block-level scans of the first dimension-reduction step in one pass: for
+// every point m of a (Q, MID, NY, NX) tensor of block aggregates (already
+// box-summed over the middle axes), box-sum each plane over its two trailing
+// axes (BDBS-Along-Dim along y and x, Sec. 5) and scan the results along the
+// block axis q without storing them:
+//   PX[q, m] = op of Gw[q', m] for q' < q,  SX[q, m] = op of Gw[q', m] for q' > q,
+//   R[m]     = op of Ga[q, m] over all q (the reduction that feeds the next level).
+// One workgroup owns a tile for all Q <= QMAX planes; the box-summed values
+// of its points stay in registers.
+// ---------------------------------------------------------------------------
+struct PlaneScanArgs {
+    const void* G;   // (Q, MID, NY, NX)
+    const void* Ga;  // (Q, M) un-box-summed aggregates (== G when MID has no axes)
+    void* PX;
+    void* SX;
+    void* R;         // (M) or null
+    i64 Q, MID, NY, NX, M;
+    int ky, kx;
+    int pxe;         // PX is stored for blocks q with q % pxe == 0 only
+    i64 tilesY, tilesX;
+};
+
+template <typename T, class Op, int KP, int QMAX>
+__global__ void __launch_bounds__(1024) k_plane_scan(PlaneScanArgs a) {
+    using C = PlaneCfg<KP>;
+    constexpr int NT = C::NT, P = C::P, SA = C::SA, SB = C::SB;
+    static_assert(QMAX % (2 * P) == 0, "rounds come in pairs");
+    __shared__ T sA[P * SA + 1];
+    __shared__ T sB[P * SB];
+    __shared__ T sW[P * NT];
+
+    const T e = Op::template id<T>();
+    const int tid = threadIdx.x;
+    i64 wg = blockIdx.x;
+    const i64 nwg = (i64)gridDim.x;
+    if ((nwg & 7) == 0) wg = (wg & 7) * (nwg >> 3) + (wg >> 3);
+    const i64 tiles = a.tilesY * a.tilesX;
+    const i64 tile = wg % tiles;
+    const int mid = (int)(wg / tiles);
+    const int ky = a.ky, kx = a.kx;
+    const int NY = (int)a.NY, NX = (int)a.NX;
+    const int Q = (int)a.Q;
+    const int y0 = (int)(tile / a.tilesX) * (C::NBY * ky);
+    const int x0 = (int)(tile % a.tilesX) * (C::NBX * kx);
+    const i64 plane = (i64)NY * NX;
+    const unsigned plane_bytes = (unsigned)(plane * (i64)sizeof(T));
+    const bool same = a.G == a.Ga;
+
+    const int pyb = tid / C::TXM, pxb = tid % C::TXM;
+    const int py = (pyb / KP) * ky + pyb % KP, px = (pxb / KP) * kx + pxb % KP;
+    const bool pvalid = pyb % KP < ky && pxb % KP < kx && y0 + py < NY && x0 + px < NX;
+    const unsigned mb = pvalid ? (unsigned)((y0 + py) * NX + x0 + px) * sizeof(T) : plane_bytes;
+    // the point's slot in the staged halo tile (its own, unfiltered value)
+    const int own = pyb * C::PA + pxb;
+
+    for (int i = tid; i < P * SA; i += NT) sA[i] = e;
+    const int rows_in = C::NBY * ky + ky - 1, cols_in = C::NBX * kx + kx - 1;
+    const int count = rows_in * cols_in;
+    int loff[C::NLOAD];
+    unsigned goff[C::NLOAD];
+#pragma unroll
+    for (int j = 0; j < C::NLOAD; ++j) {
+        const int el = tid + j * NT;
+        const int r = el / cols_in, c = el % cols_in;
+        const bool inside = el < count && y0 + r < NY && x0 + c < NX;
+        loff[j] = inside ? ((r / ky) * KP + r % ky) * C::PA + (c / kx) * KP + c % kx : P * SA;
+        goff[j] = inside ? (unsigned)((y0 + r) * NX + x0 + c) * sizeof(T) : 0u;
+    }
+    constexpr int rt1 = C::ROWS * C::NBX, ct1 = C::TXM * C::NBY;
+    int rp[C::RT], cp[C::CT];
+#pragma unroll
+    for (int i = 0; i < C::RT; ++i) {
+        const int task = tid + i * NT;
+        const int u = task / rt1, rem = task % rt1;
+        rp[i] = task < P * rt1 ? (u | ((rem / C::ROWS) << 2) | ((rem % C::ROWS) << 8)) : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < C::CT; ++i) {
+        const int task = tid + i * NT;
+        const int u = task / ct1, rem = task % ct1;
+        cp[i] = task < P * ct1 ? (u | ((rem / C::TXM) << 2) | ((rem % C::TXM) << 8)) : -1;
+    }
+    const T* __restrict__ G = (const T*)a.G;
+    const T* __restrict__ Ga = (const T*)a.Ga;
+    // plane (q, mid) of G; rounds past Q re-read plane 0 (never staged)
+    auto fetch = [&](T (&pre)[P][C::NLOAD], int q0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            const int q = q0 + u < Q ? q0 + u : 0;
+            const __amdgpu_buffer_rsrc_t pl = buf(G + ((i64)q * a.MID + mid) * plane, plane_bytes);
+#pragma unroll
+            for (int j = 0; j < C::NLOAD; ++j) pre[u][j] = bload<T>(pl, goff[j]);
+        }
+    };
+    T gw[QMAX];
+    T Rm = e;
+    auto round = [&](T (&pre)[P][C::NLOAD], int q0) __attribute__((always_inline)) {
+        const int np = Q - q0 < P ? Q - q0 : P;
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            if (u < np) {
+#pragma unroll
+                for (int j = 0; j < C::NLOAD; ++j) {
+                    const int o = loff[j] == P * SA ? P * SA : u * SA + loff[j];
+                    sA[o] = pre[u][j];
+                }
+            }
+        }
+        if (q0 + 2 * P < Q) fetch(pre, q0 + 2 * P);
+        __syncthreads();
+        // the reduction over blocks: the point's own aggregate
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            if (u < np) {
+                const T g = same ? sA[u * SA + own]
+                                 : bload<T>(buf(Ga + (i64)(q0 + u) * a.M + (i64)mid * plane,
+                                                plane_bytes), mb);
+                Rm = Op::apply(Rm, g);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < C::RT; ++i) {
+            const int pk = rp[i];
+            if (pk >= 0 && (pk & 3) < np) {
+                const int u = pk & 3, b = (pk >> 2) & 63, row = pk >> 8;
+                bdbs_block<T, Op, KP, 1, 1>(sA + u * SA + row * C::PA + b * KP,
+                                            sB + u * SB + row * C::PB + b * KP);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < C::CT; ++i) {
+            const int pk = cp[i];
+            if (pk >= 0 && (pk & 3) < np) {
+                const int u = pk & 3, b = (pk >> 2) & 63, col = pk >> 8;
+                bdbs_block<T, Op, KP, C::PB, C::TXM>(sB + u * SB + b * KP * C::PB + col,
+                                                      sW + u * NT + b * KP * C::TXM + col);
+            }
+        }
+        __syncthreads();
+    };
+    T pre0[P][C::NLOAD], pre1[P][C::NLOAD];
+    fetch(pre0, 0);
+    if (P < Q) fetch(pre1, P);
+    __syncthreads();
+#pragma unroll
+    for (int q0 = 0; q0 < QMAX; q0 += 2 * P) {
+        if (q0 < Q) {
+            round(pre0, q0);
+#pragma unroll
+            for (int u = 0; u < P; ++u) gw[q0 + u] = q0 + u < Q ? sW[u * NT + tid] : e;
+        }
+        if (q0 + P < Q) {
+            round(pre1, q0 + P);
+#pragma unroll
+            for (int u = 0; u < P; ++u) gw[q0 + P + u] = q0 + P + u < Q ? sW[u * NT + tid] : e;
+        }
+    }
+    if (!pvalid) return;
+    const i64 m = (i64)mid * plane + (i64)(y0 + py) * NX + x0 + px;
+    T* __restrict__ PX = (T*)a.PX;
+    T* __restrict__ SX = (T*)a.SX;
+    T pfx = e;
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+        if (q < Q) {
+            if (q % a.pxe == 0) PX[(i64)q * a.M + m] = pfx;
+            pfx = Op::apply(pfx, gw[q]);
+        }
+    }
+    T sfx = e;
+#pragma unroll
+    for (int q = QMAX - 1; q >= 0; --q) {
+        if (q < Q) {
+            SX[(i64)q * a.M + m] = sfx;
+            sfx = Op::apply(gw[q], sfx);
+        }
+    }
+    if (a.R) ((T*)a.R)[m] = Rm;
+}
+
+template <typename T, class Op, int KP>
+void launch_plane_scan_kp(PlaneScanArgs pa, hipStream_t st) {
+    using C = PlaneCfg<KP>;
+    const i64 ty = (i64)C::NBY * pa.ky, tx = (i64)C::NBX * pa.kx;
+    pa.tilesY = (pa.NY + ty - 1) / ty;
+    pa.tilesX = (pa.NX + tx - 1) / tx;
+    const i64 grid = pa.tilesY * pa.tilesX * pa.MID;
+    hipLaunchKernelGGL((k_plane_scan<T, Op, KP, 32>), dim3((unsigned)grid), dim3(C::NT), 0, st,
+                       pa);
+}
+
+template <typename T, class Op>
+void launch_plane_scan(const T* G, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 MID, i64 NY,
+                       i64 NX, i64 ky, i64 kx, i64 pxe, hipStream_t st) {
+    KTimer timer("k_plane_scan", st);
+    PlaneScanArgs pa{};
+    pa.G = G; pa.Ga = Ga; pa.PX = PX; pa.SX = SX; pa.R = R;
+    pa.Q = Q; pa.MID = MID; pa.NY = NY; pa.NX = NX; pa.M = MID * NY * NX;
+    pa.ky = (int)ky; pa.kx = (int)kx; pa.pxe = (int)pxe;
+    const i64 km = ky > kx ? ky : kx;
+    if (km <= 2) launch_plane_scan_kp<T, Op, 2>(pa, st);
+    else if (km <= 4) launch_plane_scan_kp<T, Op, 4>(pa, st);
+    else if (km <= 8) launch_plane_scan_kp<T, Op, 8>(pa, st);
+    else launch_plane_scan_kp<T, Op, 16>(pa, st);
+}
+
 template <typename T, class Op, int KP>
 void launch_plane_bdbs_kp(Plane2Args pa, hipStream_t st) {
     using C = PlaneCfg<KP>;
@@ -563,12 +788,7 @@ void launch_plane_kernel(PlaneArgs pa, hipStream_t st) {
     pa.tilesY = (pa.NY + ty - 1) / ty;
     pa.tilesX = (pa.NX + tx - 1) / tx;
     const i64 tiles = pa.tilesY * pa.tilesX * pa.MID;
-    // enough workgroups to cover every CU; each run of blocks reads one extra
-    // block of planes
-    i64 nseg = (256 + tiles - 1) / tiles;
-    if (nseg > pa.Q) nseg = pa.Q;
-    if (nseg < 1) nseg = 1;
-    pa.segblocks = (pa.Q + nseg - 1) / nseg;
+    pa.segblocks = plane_run_blocks(pa.Q, tiles);
     pa.nseg = (pa.Q + pa.segblocks - 1) / pa.segblocks;
     const i64 grid = tiles * pa.nseg;
     // whole blocks: every block of every run has exactly K0B planes

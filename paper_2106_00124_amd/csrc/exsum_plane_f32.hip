@@ -17,6 +17,10 @@ bool plane_eligible(int d, const i64* n, const i64* k, int es) {
     return true;
 }
 
+i64 plane_axis0_run_blocks(i64 Q, i64 MID, i64 NY, i64 NX, i64 ky, i64 kx) {
+    return plane_run_blocks(Q, plane_tiles(NY, NX, ky, kx) * MID);
+}
+
 bool plane2_eligible(i64 NY, i64 NX, i64 ky, i64 kx, int es) {
     return es == 4 && ky <= 16 && kx <= 16 && NY * NX * es < ((i64)1 << 31);
 }
@@ -31,4 +35,8 @@ template void launch_plane_bdbs<float, OpSum>(const float*, float*, i64, i64, i6
                                              hipStream_t);
 template void launch_plane_bdbs<float, OpMax>(const float*, float*, i64, i64, i64, i64, i64,
                                              hipStream_t);
+template void launch_plane_scan<float, OpSum>(const float*, const float*, float*, float*, float*, i64, i64,
+                                            i64, i64, i64, i64, i64, hipStream_t);
+template void launch_plane_scan<float, OpMax>(const float*, const float*, float*, float*, float*, i64, i64,
+                                            i64, i64, i64, i64, i64, hipStream_t);
 }  // namespace exs

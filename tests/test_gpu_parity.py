@@ -62,6 +62,11 @@ PLANE_CASES = [
     ((50, 20, 100), (12, 2, 16)),
     ((33, 64, 31), (16, 5, 3)),
     ((65, 47, 48), (13, 16, 9)),
+    # 32 blocks along axis 0 (one-pass block scans) and 33 (separate passes)
+    ((64, 40, 36), (2, 5, 3)),
+    ((66, 40, 36), (2, 5, 3)),
+    # 64 tiles: four runs of eight blocks along axis 0
+    ((64, 256, 256), (2, 16, 16)),
 ]
 
 
