@@ -70,6 +70,18 @@ struct ListSink {
             push(s, 1);
             return;
         }
+        const i64 rcb = I == 1 ? rows_blocks(O, n, k, ROWS_MIN_TASKS) : 0;
+        if (I == 1 && rows_tasks(O, n, k, rcb) >= ROWS_MIN_TASKS) {
+            // rows of the contiguous axis of a large tensor: wavefront tasks
+            // through LDS
+            s.kind = SK_BDBSR;
+            const i64 nbr = (n + k - 1) / k;
+            s.cb = rcb;
+            s.nchunks = (nbr + s.cb - 1) / s.cb;
+            s.ntasks = ((O + ROWS_PER_TASK - 1) / ROWS_PER_TASK) * s.nchunks;
+            push(s, kb);
+            return;
+        }
         s.kind = SK_BDBS;
         const i64 nb = (n + k - 1) / k, cols = O * I;
         i64 nch = (cfg.min_tasks + cols - 1) / cols;
@@ -182,6 +194,7 @@ struct Launch {
     size_t first;  // index of the first step in the device array
     int nsteps;
     i64 total;
+    size_t lds;    // dynamic LDS bytes per workgroup (row tasks)
 };
 
 }  // namespace exs
@@ -246,11 +259,15 @@ static exs_status build(exs_batch* b, void* ws, const TuneCfg& cfg) {
             L.first = all.size();
             L.nsteps = (int)g.second.size();
             i64 tb = 0;
+            L.lds = 0;
             for (const Rec* r : g.second) {
                 Step s = r->s;
                 s.task_begin = tb;
                 tb += s.ntasks;
                 all.push_back(s);
+                if (s.kind == SK_BDBSR)
+                    L.lds = std::max(L.lds, (size_t)ROWS_PER_TASK * rows_pitch(s.cb, s.k) *
+                                                dtype_size(L.dtype));
             }
             L.total = tb;
             b->items += (i64)g.second.size();
@@ -276,11 +293,17 @@ static void enqueue(exs_batch* b, const TuneCfg& cfg, hipStream_t st) {
     const i64 cap = (i64)cfg.wg_per_cu * b->num_cu;
     for (auto& ph : b->phases)
         for (auto& L : ph) {
-            i64 g = (L.total + 255) / 256;
-            if (g > cap) g = cap;
+            i64 g;
+            if (L.kind == SK_BDBSR) {
+                // one wavefront per workgroup, one task per wavefront at a time
+                g = L.total < 4 * cap ? L.total : 4 * cap;
+            } else {
+                g = (L.total + 255) / 256;
+                if (g > cap) g = cap;
+            }
             if (g < 1) g = 1;
             launch_worklist(L.dtype, L.op, L.kind, L.kb, b->dev_steps + L.first, L.nsteps, L.total,
-                            (int)g, st);
+                            (int)g, L.lds, st);
         }
 }
 

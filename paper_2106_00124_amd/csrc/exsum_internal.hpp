@@ -28,7 +28,7 @@ inline int bucket_for(i64 k) {
 // work-list launch of the batched form (exsum_worklist.hip): `steps` is a
 // device array of Step (exsum_tasks.hpp)
 void launch_worklist(int dtype, int op, int kind, int kb, const void* steps, int nsteps, i64 total,
-                     int grid, hipStream_t st);
+                     int grid, size_t lds, hipStream_t st);
 
 // generic-path launchers (exsum_kernels.hip)
 template <typename T, class Op>

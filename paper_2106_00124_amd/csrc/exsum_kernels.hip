@@ -31,6 +31,13 @@ __global__ __launch_bounds__(256) void k_bdbs(const T* __restrict__ in, T* __res
     if (idx < O * nchunks * I) task_bdbs<T, Op, KB>(in, out, O, n, I, k, cb, nchunks, idx);
 }
 
+template <typename T, class Op, int KB>
+__global__ __launch_bounds__(64) void k_bdbs_rows(const T* __restrict__ in, T* __restrict__ out,
+                                                  i64 O, i64 n, int k, i64 cb, i64 nchunks) {
+    extern __shared__ __align__(16) unsigned char exs_rows_lds[];
+    task_bdbs_rows<T, Op, KB>(in, out, O, n, k, cb, nchunks, blockIdx.x, (T*)exs_rows_lds);
+}
+
 template <typename T, class Op>
 __global__ __launch_bounds__(256) void k_bdbs_2sweep(const T* __restrict__ in,
                                                      T* __restrict__ out, i64 O, i64 n,
@@ -173,6 +180,28 @@ void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st
         return;
     }
     const i64 nb = (n + k - 1) / k;
+    const i64 rcb = I == 1 ? rows_blocks(O, n, k, ROWS_MIN_TASKS) : 0;
+    if (I == 1 && rows_tasks(O, n, k, rcb) >= ROWS_MIN_TASKS) {
+        // rows of the contiguous axis, enough of them to fill the GPU with
+        // wavefront tasks: staged through LDS (fewer, coalesced transactions;
+        // small tensors keep the one-row-per-lane kernel, which has the
+        // shorter latency chain)
+        const i64 cb = rcb;
+        const i64 nch = (nb + cb - 1) / cb;
+        const i64 tasks = rows_tasks(O, n, k, cb);
+        const size_t lds = (size_t)ROWS_PER_TASK * rows_pitch(cb, k) * sizeof(T);
+#define EXS_ROWS_CASE(KB)                                                                     \
+    case KB:                                                                                  \
+        hipLaunchKernelGGL((k_bdbs_rows<T, Op, KB>), dim3((unsigned)tasks), dim3(64), lds, st, \
+                           in, out, O, n, (int)k, cb, nch);                                   \
+        break;
+        switch (kb) {
+            EXS_ROWS_CASE(1) EXS_ROWS_CASE(2) EXS_ROWS_CASE(4) EXS_ROWS_CASE(8)
+            EXS_ROWS_CASE(16) EXS_ROWS_CASE(32) EXS_ROWS_CASE(64)
+        }
+#undef EXS_ROWS_CASE
+        return;
+    }
     const i64 cols = O * I;
     i64 nchunks = (65536 + cols - 1) / cols;
     if (nchunks > nb) nchunks = nb;

@@ -21,7 +21,8 @@ enum StepKind : int {
     SK_SCAN = 3,   // exclusive block prefix/suffix and the reduction of axis 0
     SK_AX0 = 4,    // axis-0 stream: excluded and/or included sums (k0 <= 64)
     SK_EX2 = 5,    // axis-0 excluded part, two sweeps (any k0)
-    SK_NKINDS = 6
+    SK_BDBSR = 6,  // BDBS along the contiguous axis through LDS (k <= 64; wavefront tasks)
+    SK_NKINDS = 7
 };
 
 // One step of the generic path.  Pointers are device pointers; the meaning
@@ -208,6 +209,133 @@ __device__ __forceinline__ void task_ex2(const T* __restrict__ W, const T* __res
         exc[x * M + m] = Op::apply(P, exc[x * M + m]);
         P = Op::apply(P, W[x * M + m]);
     }
+}
+
+// BDBS along the contiguous axis (rows of n elements, I == 1).  Lanes that
+// each walk their own row would touch 64 rows per load; instead one wavefront
+// (a workgroup of 64 threads) owns 64 rows and a run of cb blocks: the tile,
+// with the k - 1 columns of the next block, is staged in LDS by coalesced row
+// loads, each lane box-sums its row from LDS (block suffixes in registers, as
+// in bdbs_row), writes the results in place, and the tile leaves by coalesced
+// row stores.  LDS: 64 x rows_pitch(cb, k) elements (odd pitch: no bank
+// conflicts between lanes reading their rows).
+constexpr int ROWS_PER_TASK = 64;
+__host__ __device__ inline int rows_pitch(i64 cb, i64 k) { return (int)((cb * k + k - 1) | 1); }
+
+// Row tasks pay off once they fill the GPU (four wavefronts per CU).
+constexpr i64 ROWS_MIN_TASKS = 1024;
+
+inline i64 rows_tasks(i64 O, i64 n, i64 k, i64 cb) {
+    const i64 nb = (n + k - 1) / k;
+    return ((O + ROWS_PER_TASK - 1) / ROWS_PER_TASK) * ((nb + cb - 1) / cb);
+}
+
+// Blocks per row task: at most 64 columns, fewer while there are fewer than
+// min_tasks tasks.
+inline i64 rows_blocks(i64 O, i64 n, i64 k, i64 min_tasks) {
+    const i64 nb = (n + k - 1) / k;
+    i64 cb = 64 / k > 1 ? 64 / k : 1;
+    if (cb > nb) cb = nb;
+    const i64 groups = (O + ROWS_PER_TASK - 1) / ROWS_PER_TASK;
+    while (cb > 1 && groups * ((nb + cb - 1) / cb) < min_tasks) cb = (cb + 1) / 2;
+    return cb;
+}
+
+template <typename T, class Op, int KB>
+__device__ __forceinline__ void task_bdbs_rows(const T* __restrict__ in, T* __restrict__ out,
+                                               i64 O, i64 n, int k, i64 cb, i64 nchunks,
+                                               i64 task, T* __restrict__ lds) {
+    const int lane = threadIdx.x;
+    const T e = Op::template id<T>();
+    const i64 g = task / nchunks, c = task % nchunks;
+    const i64 nb = (n + k - 1) / k;
+    const i64 b0 = c * cb;
+    const i64 b1 = b0 + cb < nb ? b0 + cb : nb;
+    const i64 col0 = b0 * k;
+    const int LW = rows_pitch(cb, k);
+    const i64 rin = (b1 - b0) * k + k - 1, rout = (b1 - b0) * k;
+    const int win = (int)(rin < n - col0 ? rin : n - col0);
+    const int wout = (int)(rout < n - col0 ? rout : n - col0);
+    const i64 row0 = g * ROWS_PER_TASK;
+    // stage the tile (identity past the row end and in the unused pitch);
+    // LW <= 127, so two 64-column passes cover a row.  Loads are issued in
+    // batches of RB rows before any of them is written to LDS.
+    constexpr int RB = 32;
+#pragma unroll
+    for (int r0 = 0; r0 < ROWS_PER_TASK; r0 += RB) {
+        T v[RB][2];
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) {
+            const i64 row = row0 + r0 + rr;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int cc = lane + 64 * h;
+                v[rr][h] = (row < O && cc < win) ? in[row * n + col0 + cc] : e;
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int cc = lane + 64 * h;
+                if (cc < LW) lds[(r0 + rr) * LW + cc] = v[rr][h];
+            }
+        }
+    }
+    __syncthreads();
+    T* my = lds + lane * LW;
+    T cur[KB], nxt[KB];
+#pragma unroll
+    for (int r = 0; r < KB; ++r) cur[r] = r < k ? my[r] : e;
+    {
+        T s = e;
+#pragma unroll
+        for (int r = KB - 1; r >= 0; --r) {
+            if (r < k) { s = Op::apply(cur[r], s); cur[r] = s; }
+        }
+    }
+    for (i64 b = b0; b < b1; ++b) {
+        const int base = (int)(b - b0) * k;
+#pragma unroll
+        for (int r = 0; r < KB; ++r) nxt[r] = (r < k && base + k + r < LW) ? my[base + k + r] : e;
+        T p = e;
+#pragma unroll
+        for (int r = 0; r < KB; ++r) {
+            if (r < k) {
+                T v = cur[r];
+                if (r > 0) { p = Op::apply(p, nxt[r - 1]); v = Op::apply(v, p); }
+                my[base + r] = v;
+            }
+        }
+        T s = e;
+#pragma unroll
+        for (int r = KB - 1; r >= 0; --r) {
+            if (r < k) { s = Op::apply(nxt[r], s); cur[r] = s; }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r0 = 0; r0 < ROWS_PER_TASK; r0 += RB) {
+        T v[RB][2];
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int cc = lane + 64 * h;
+                v[rr][h] = cc < LW ? lds[(r0 + rr) * LW + cc] : e;
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) {
+            const i64 row = row0 + r0 + rr;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int cc = lane + 64 * h;
+                if (row < O && cc < wout) out[row * n + col0 + cc] = v[rr][h];
+            }
+        }
+    }
+    __syncthreads();  // the tile is reused by the next task of this workgroup
 }
 
 // Dispatch one task of a recorded step (KB: the register bucket of the step,

@@ -29,6 +29,40 @@ __global__ __launch_bounds__(256) void k_worklist(const Step* __restrict__ steps
     }
 }
 
+// Row BDBS tasks (SK_BDBSR) take a whole wavefront each: workgroups of 64
+// threads walk the task range with a workgroup stride; the LDS tile is
+// dynamic (sized for the widest step of the launch).
+template <typename T, class Op, int KB>
+__global__ __launch_bounds__(64) void k_worklist_rows(const Step* __restrict__ steps, int nsteps,
+                                                      i64 total) {
+    extern __shared__ __align__(16) unsigned char exs_wl_lds[];
+    for (i64 t = blockIdx.x; t < total; t += gridDim.x) {
+        int lo = 0, hi = nsteps - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (steps[mid].task_begin <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const Step s = steps[lo];
+        task_bdbs_rows<T, Op, KB>((const T*)s.in0, (T*)s.out0, s.O, s.n, s.k, s.cb, s.nchunks,
+                                  t - s.task_begin, (T*)exs_wl_lds);
+    }
+}
+
+template <typename T, class Op>
+static void launch_rows(int kb, const Step* steps, int nsteps, i64 total, int grid, size_t lds,
+                        hipStream_t st) {
+#define EXS_WLR(KB)                                                                          \
+    case KB:                                                                                 \
+        hipLaunchKernelGGL((k_worklist_rows<T, Op, KB>), dim3(grid), dim3(64), lds, st, steps, \
+                           nsteps, total);                                                   \
+        return;
+    switch (kb) {
+        EXS_WLR(1) EXS_WLR(2) EXS_WLR(4) EXS_WLR(8) EXS_WLR(16) EXS_WLR(32) EXS_WLR(64)
+    }
+#undef EXS_WLR
+}
+
 template <typename T, class Op, int KIND>
 static void launch_kb(int kb, const Step* steps, int nsteps, i64 total, int grid, hipStream_t st) {
 #define EXS_WL(KB)                                                                            \
@@ -49,8 +83,9 @@ static void launch_kb(int kb, const Step* steps, int nsteps, i64 total, int grid
 
 template <typename T, class Op>
 static void launch_kind(int kind, int kb, const Step* steps, int nsteps, i64 total, int grid,
-                        hipStream_t st) {
+                        size_t lds, hipStream_t st) {
     switch (kind) {
+        case SK_BDBSR: launch_rows<T, Op>(kb, steps, nsteps, total, grid, lds, st); break;
         case SK_BDBS: launch_kb<T, Op, SK_BDBS>(kb, steps, nsteps, total, grid, st); break;
         case SK_BDBS2: launch_kb<T, Op, SK_BDBS2>(kb, steps, nsteps, total, grid, st); break;
         case SK_AGG: launch_kb<T, Op, SK_AGG>(kb, steps, nsteps, total, grid, st); break;
@@ -62,19 +97,19 @@ static void launch_kind(int kind, int kb, const Step* steps, int nsteps, i64 tot
 
 template <typename T>
 static void launch_op(int op, int kind, int kb, const Step* steps, int nsteps, i64 total, int grid,
-                      hipStream_t st) {
-    if (op == EXS_SUM) launch_kind<T, OpSum>(kind, kb, steps, nsteps, total, grid, st);
-    else launch_kind<T, OpMax>(kind, kb, steps, nsteps, total, grid, st);
+                      size_t lds, hipStream_t st) {
+    if (op == EXS_SUM) launch_kind<T, OpSum>(kind, kb, steps, nsteps, total, grid, lds, st);
+    else launch_kind<T, OpMax>(kind, kb, steps, nsteps, total, grid, lds, st);
 }
 
 void launch_worklist(int dtype, int op, int kind, int kb, const void* steps, int nsteps, i64 total,
-                     int grid, hipStream_t st) {
+                     int grid, size_t lds, hipStream_t st) {
     const Step* s = (const Step*)steps;
     switch (dtype) {
-        case EXS_F32: launch_op<float>(op, kind, kb, s, nsteps, total, grid, st); break;
-        case EXS_F64: launch_op<double>(op, kind, kb, s, nsteps, total, grid, st); break;
-        case EXS_I32: launch_op<int>(op, kind, kb, s, nsteps, total, grid, st); break;
-        case EXS_I64: launch_op<long long>(op, kind, kb, s, nsteps, total, grid, st); break;
+        case EXS_F32: launch_op<float>(op, kind, kb, s, nsteps, total, grid, lds, st); break;
+        case EXS_F64: launch_op<double>(op, kind, kb, s, nsteps, total, grid, lds, st); break;
+        case EXS_I32: launch_op<int>(op, kind, kb, s, nsteps, total, grid, lds, st); break;
+        case EXS_I64: launch_op<long long>(op, kind, kb, s, nsteps, total, grid, lds, st); break;
     }
 }
 

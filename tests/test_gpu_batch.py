@@ -29,6 +29,9 @@ def _mixed_items(seed, count):
     # a long box (two-sweep kernels) and a 1-element tensor
     items.append(((300, 7), (100, 3), "i32", "sum", "both", 11))
     items.append(((1, 1, 1), (1, 1, 1), "f32", "max", "both", 12))
+    # many rows along the contiguous axis (LDS-staged row tasks)
+    items.append(((40000, 70), (3, 9), "f32", "sum", "both", 13))
+    items.append(((300, 200, 64), (5, 4, 33), "i32", "max", "both", 14))
     return items
 
 
