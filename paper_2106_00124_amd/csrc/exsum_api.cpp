@@ -141,6 +141,10 @@ struct EagerSink {
     void blockagg(const T* X, T* Ga, i64 n0, i64 M, i64 k0, i64 Q) {
         launch_blockagg<T, Op>(X, Ga, n0, M, k0, Q, st);
     }
+    bool small1d_ok(i64 n) const { return ex1d_small_ok(n); }
+    void ex1d_small(const T* R, T* exc, i64 n, i64 k) {
+        launch_ex1d_small<T, Op>(R, exc, n, k, st);
+    }
     void blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M) {
         launch_blockscan<T, Op>(Gw, Ga, PX, SX, R, Q, M, st);
     }

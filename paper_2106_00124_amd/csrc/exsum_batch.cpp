@@ -54,6 +54,9 @@ struct ListSink {
     TuneCfg cfg;
     bool fused_ok = false;
     void level(int) {}
+    // the single-workgroup kernel for a short last level has no work-list form
+    bool small1d_ok(i64) const { return false; }
+    void ex1d_small(const T*, T*, i64, i64) {}
     void push(const Step& s, int kb) { out->push_back(Rec{s, dtype, op, kb}); }
     void bdbs(const T* in, T* o, i64 O, i64 n, i64 I, i64 k) {
         Step s{};

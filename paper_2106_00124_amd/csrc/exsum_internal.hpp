@@ -33,6 +33,10 @@ void launch_worklist(int dtype, int op, int kind, int kb, const void* steps, int
 // generic-path launchers (exsum_kernels.hip)
 template <typename T, class Op>
 void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st);
+// excluded sums of a 1-D tensor of at most 8192 elements in one workgroup
+bool ex1d_small_ok(i64 n);
+template <typename T, class Op>
+void launch_ex1d_small(const T* R, T* exc, i64 n, i64 k, hipStream_t st);
 template <typename T, class Op>
 void launch_blockagg(const T* X, T* Ga, i64 n0, i64 M, i64 k0, i64 Q, hipStream_t st);
 template <typename T, class Op>

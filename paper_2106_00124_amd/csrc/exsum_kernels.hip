@@ -38,6 +38,68 @@ __global__ __launch_bounds__(64) void k_bdbs_rows(const T* __restrict__ in, T* _
     task_bdbs_rows<T, Op, KB>(in, out, O, n, k, cb, nchunks, blockIdx.x, (T*)exs_rows_lds);
 }
 
+// The excluded sums of a short 1-D tensor (the last dimension-reduction
+// level, Sec. 5: only the prefix before x and the suffix from x + k remain) in
+// one workgroup: the tensor is staged in LDS, each thread scans its run of
+// EX1_PER consecutive elements, a workgroup scan of the run totals gives the
+// offsets, and Exc[x] = prefix(x - 1) op suffix(x + k).
+constexpr int EX1_THREADS = 1024, EX1_PER = 8, EX1_MAX = EX1_THREADS * EX1_PER;
+
+template <typename T, class Op>
+__global__ __launch_bounds__(1024) void k_ex1d_small(const T* __restrict__ R, T* __restrict__ exc,
+                                                     int n, int k) {
+    __shared__ T pre[EX1_MAX];
+    __shared__ T suf[EX1_MAX];
+    __shared__ T tot[EX1_THREADS];
+    const T e = Op::template id<T>();
+    const int t = threadIdx.x;
+    const int b = t * EX1_PER;
+    T v[EX1_PER];
+#pragma unroll
+    for (int r = 0; r < EX1_PER; ++r) v[r] = b + r < n ? R[b + r] : e;
+    // run totals, then an inclusive scan of them (Hillis-Steele in LDS)
+    T run = e;
+#pragma unroll
+    for (int r = 0; r < EX1_PER; ++r) run = Op::apply(run, v[r]);
+    tot[t] = run;
+    __syncthreads();
+    for (int off = 1; off < EX1_THREADS; off <<= 1) {
+        const T add = t >= off ? tot[t - off] : e;
+        __syncthreads();
+        tot[t] = Op::apply(add, tot[t]);
+        __syncthreads();
+    }
+    // inclusive prefix of every element: (scan of the runs before) op run
+    T p = t > 0 ? tot[t - 1] : e;
+#pragma unroll
+    for (int r = 0; r < EX1_PER; ++r) {
+        p = Op::apply(p, v[r]);
+        pre[b + r] = p;
+    }
+    __syncthreads();
+    // the suffix: the same scan in the reverse order of the runs
+    tot[t] = run;
+    __syncthreads();
+    for (int off = 1; off < EX1_THREADS; off <<= 1) {
+        const T add = t + off < EX1_THREADS ? tot[t + off] : e;
+        __syncthreads();
+        tot[t] = Op::apply(tot[t], add);
+        __syncthreads();
+    }
+    T q = t + 1 < EX1_THREADS ? tot[t + 1] : e;
+#pragma unroll
+    for (int r = EX1_PER - 1; r >= 0; --r) {
+        q = Op::apply(v[r], q);
+        suf[b + r] = q;
+    }
+    __syncthreads();
+    for (int x = t; x < n; x += EX1_THREADS) {
+        const T lo = x >= 1 ? pre[x - 1] : e;
+        const T hi = x + k < n ? suf[x + k] : e;
+        exc[x] = Op::apply(lo, hi);
+    }
+}
+
 template <typename T, class Op>
 __global__ __launch_bounds__(256) void k_bdbs_2sweep(const T* __restrict__ in,
                                                      T* __restrict__ out, i64 O, i64 n,
@@ -222,6 +284,15 @@ void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st
 }
 
 template <typename T, class Op>
+void launch_ex1d_small(const T* R, T* exc, i64 n, i64 k, hipStream_t st) {
+    KTimer timer("k_ex1d_small", st);
+    hipLaunchKernelGGL((k_ex1d_small<T, Op>), dim3(1), dim3(EX1_THREADS), 0, st, R, exc, (int)n,
+                       (int)k);
+}
+
+bool ex1d_small_ok(i64 n) { return n <= EX1_MAX; }
+
+template <typename T, class Op>
 void launch_blockagg(const T* X, T* Ga, i64 n0, i64 M, i64 k0, i64 Q, hipStream_t st) {
     KTimer timer("k_blockagg", st);
     if constexpr (sizeof(T) == 4) {
@@ -285,6 +356,7 @@ void launch_fill(void* out, i64 count, int dtype, int kind, uint64_t seed, i64 l
 }
 
 #define EXS_INSTANTIATE(T, OP)                                                                 \
+    template void launch_ex1d_small<T, OP>(const T*, T*, i64, i64, hipStream_t);               \
     template void launch_bdbs<T, OP>(const T*, T*, i64, i64, i64, i64, hipStream_t);           \
     template void launch_blockagg<T, OP>(const T*, T*, i64, i64, i64, i64, hipStream_t);       \
     template void launch_blockscan<T, OP>(const T*, const T*, T*, T*, T*, i64, i64,            \

@@ -139,9 +139,13 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
 
     // top-down: block aggregates, their box-sums over the other axes, block
     // scans, and the reduction that feeds the next level
+    // the last level is 1-D; when short, one workgroup computes its excluded
+    // sums directly from R_{d-1} (no block passes)
+    const bool last_small = d >= 2 && sink.small1d_ok(n[d - 1]);
     for (int j = 0; j < d; ++j) {
         const int dj = d - j;
         const T* src = j == 0 ? A : R[j];
+        if (j == d - 1 && last_small) break;
         sink.level(j);
         if (!dry) sink.blockagg(src, Ga, n[j], M[j], k[j], Q[j]);
         i64 gn[EXS_MAX_RANK], gk[EXS_MAX_RANK];
@@ -184,6 +188,10 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
         sink.level(j);
         T* out = j == 0 ? exc : tb[j % 2];
         const T* Trest = j == d - 1 ? nullptr : tb[(j + 1) % 2];
+        if (j == d - 1 && last_small) {
+            if (!dry) sink.ex1d_small(src, out, n[j], k[j]);
+            continue;
+        }
         if (j == 0 && fused) {
             const T* X0 = filter_axes<T>(A, n, k, d, 1, d - 3, wb0, wb1, dry, sink);
             if (!dry)

@@ -26,6 +26,9 @@ CASES = [
     ((6, 5, 4, 3, 2), (3, 2, 4, 1, 2)),
     ((3, 2, 3, 2, 3, 2), (2, 2, 1, 2, 3, 1)),
     ((2, 2, 2, 2, 2, 2, 2, 3), (1, 2, 2, 1, 2, 2, 1, 2)),
+    # a last level longer than the one-workgroup kernel takes
+    ((3, 9000), (2, 5)),
+    ((2, 3, 8193), (1, 2, 100)),
     # enough rows along the contiguous axis for the LDS-staged row kernel
     ((65536, 130), (3, 5)),
     ((256, 64, 200), (2, 3, 64)),
