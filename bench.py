@@ -36,6 +36,8 @@ def parse():
     p.add_argument("--no-check", action="store_true")
     p.add_argument("--copy-probe", action="store_true",
                    help="also time a plain device copy of the input (bandwidth ceiling)")
+    p.add_argument("--no-weak", action="store_true",
+                   help="skip the weak excluded sums (total - included) for +")
     p.add_argument("--no-batched", action="store_true", help="skip the batched form")
     p.add_argument("--no-served", action="store_true", help="skip the serving form")
     p.add_argument("--batch-count", type=int, default=512)
@@ -145,6 +147,8 @@ def main():
     a = torch.from_numpy(a_host).to(dev)
     outs = {op: (torch.empty_like(a), torch.empty_like(a)) for op in w.ops}
     ws_bytes = max(P.workspace_size(w.shape, w.box, dt, op, "both") for op in w.ops)
+    if "sum" in w.ops:
+        ws_bytes = max(ws_bytes, P.workspace_size(w.shape, w.box, dt, "sum", "both_weak"))
     ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
     L = _lib.lib()
@@ -205,6 +209,30 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         per_op[op] = e0.elapsed_time(e1) / max(1, args.steps // 2)
+
+    # weak excluded sums for + (total - included), for the record: timed and
+    # spot-checked on their own, not part of the step
+    weak = None
+    if "sum" in w.ops and not args.no_weak:
+        wi, we = torch.empty_like(a), torch.empty_like(a)
+        P.run(a, w.box, "sum", "both_weak", inc_out=wi, exc_out=we, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = max(1, args.steps // 2)
+        e0.record(stream)
+        for _ in range(reps):
+            P.run(a, w.box, "sum", "both_weak", inc_out=wi, exc_out=we, workspace=ws,
+                  stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wms = e0.elapsed_time(e1) / reps
+        weak = {"op": "sum", "outputs": ["included", "excluded (total - included)"],
+                "ms_per_op": round(wms, 4), "gelem_per_s": round(N / (wms * 1e-3) / 1e9, 3),
+                "strong_ms_per_op": round(per_op["sum"], 4)}
+        if not args.no_check:
+            weak["check"] = spot_check(a_host, w, {"sum": (wi, we)}, np, ops=("sum",))
+        del wi, we
 
     excl_elems_per_step = N * len(w.ops)
     value = excl_elems_per_step / (ms_per_step * 1e-3) / 1e9
@@ -283,6 +311,7 @@ def main():
         "cpu_baseline": cpu,
         "copy_probe": copy,
         "check": check,
+        "weak": weak,
         "batched": batched,
         "served": served,
     }
@@ -522,7 +551,7 @@ def bench_served(args, P, _lib, torch, np):
     return res
 
 
-def spot_check(a_host, w, outs, np):
+def spot_check(a_host, w, outs, np, ops=None):
     import oracle
     from tests import tolerance
     o = oracle.default()
@@ -530,7 +559,7 @@ def spot_check(a_host, w, outs, np):
     pts = rng.integers(0, w.n, size=2000)
     pts = np.concatenate([pts, [0, w.n - 1]])
     res = {}
-    for op in w.ops:
+    for op in (ops or w.ops):
         inc, exc = (t.reshape(-1)[pts].cpu().numpy() for t in outs[op])
         ri = o.point_inc(a_host, w.box, op, w.dtype, pts)
         re_ = o.point_exc(a_host, w.box, op, w.dtype, pts)

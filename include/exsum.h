@@ -68,11 +68,20 @@ typedef enum { EXS_SUM = 0, EXS_MAX = 1 } exs_op;
 /* mode bit-mask */
 #define EXS_INCLUDED 1u
 #define EXS_EXCLUDED 2u
+/* With EXS_EXCLUDED and op EXS_SUM only: compute the excluded sums as the
+ * "weak" excluded sums total - included (the BDBSC route that Sec. 1 of the
+ * paper contrasts with the strong, inverse-free box-complement; its Sec. 6
+ * measures both).  Exact for the integer types (wrapping); for floating point
+ * the total is accumulated in FP64 and the subtraction is done in the element
+ * type, so cells whose excluded sum nearly cancels lose relative accuracy.
+ * With op EXS_MAX: EXS_EUNSUPPORTED (max has no inverse).  Not accepted by
+ * exs_batch_create (EXS_EUNSUPPORTED). */
+#define EXS_WEAK 4u
 
 /* One included/excluded-sums problem on one tensor.
  *   d            rank, 1..EXS_MAX_RANK
  *   dtype, op    element type and operator (see above)
- *   mode         EXS_INCLUDED, EXS_EXCLUDED or both
+ *   mode         EXS_INCLUDED, EXS_EXCLUDED or both, optionally | EXS_WEAK
  *   dims[0..d)   tensor side lengths n_i
  *   box[0..d)    box side lengths k_i
  *   in_dev       input tensor, prod(dims) elements

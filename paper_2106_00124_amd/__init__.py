@@ -33,7 +33,10 @@ def _dtype_code(t):
 
 _OPS = {"sum": _lib.SUM, "+": _lib.SUM, "max": _lib.MAX}
 _MODES = {"inc": _lib.INCLUDED, "included": _lib.INCLUDED, "exc": _lib.EXCLUDED,
-          "excluded": _lib.EXCLUDED, "both": _lib.INCLUDED | _lib.EXCLUDED}
+          "excluded": _lib.EXCLUDED, "both": _lib.INCLUDED | _lib.EXCLUDED,
+          # weak excluded sums (total - included), + only
+          "weak": _lib.EXCLUDED | _lib.WEAK,
+          "both_weak": _lib.INCLUDED | _lib.EXCLUDED | _lib.WEAK}
 
 
 def _mode_code(mode):

@@ -24,6 +24,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -55,8 +56,15 @@ exs_status validate_job(const exs_job* job, bool check_ptrs) {
         return set_error(EXS_EINVAL, "rank d must be in 1..8");
     if (dtype_size(job->dtype) == 0) return set_error(EXS_EINVAL, "unknown dtype");
     if (job->op != EXS_SUM && job->op != EXS_MAX) return set_error(EXS_EINVAL, "unknown op");
-    if (job->mode == 0 || (job->mode & ~(EXS_INCLUDED | EXS_EXCLUDED)))
-        return set_error(EXS_EINVAL, "mode must be EXS_INCLUDED and/or EXS_EXCLUDED");
+    if (job->mode == 0 || (job->mode & ~(EXS_INCLUDED | EXS_EXCLUDED | EXS_WEAK)))
+        return set_error(EXS_EINVAL, "mode must be EXS_INCLUDED and/or EXS_EXCLUDED [| EXS_WEAK]");
+    if (job->mode & EXS_WEAK) {
+        if (!(job->mode & EXS_EXCLUDED))
+            return set_error(EXS_EINVAL, "EXS_WEAK needs EXS_EXCLUDED");
+        if (job->op != EXS_SUM)
+            return set_error(EXS_EUNSUPPORTED,
+                             "weak excluded sums subtract, and max has no inverse");
+    }
     __int128 N = 1;
     for (int i = 0; i < job->d; ++i) {
         if (job->dims[i] < 1) return set_error(EXS_EINVAL, "every dims[i] must be >= 1");
@@ -142,6 +150,15 @@ struct EagerSink {
         launch_blockagg<T, Op>(X, Ga, n0, M, k0, Q, st);
     }
     bool small1d_ok(i64 n) const { return ex1d_small_ok(n); }
+    void total(const T* X, i64 N, void* parts, T* tot) { launch_total<T>(X, N, parts, tot, st); }
+    void weak_exc(const T* inc, const T* tot, T* exc, i64 N) {
+        launch_weak_exc<T>(inc, tot, exc, N, st);
+    }
+    void plane_weak(const T* X, T* inc, const T* tot, T* wexc, i64 n0, i64 MID, i64 NY, i64 NX,
+                    i64 k0, i64 ky, i64 kx) {
+        if constexpr (sizeof(T) == 4 && std::is_same<Op, OpSum>::value)
+            launch_plane_weak<T, Op>(X, inc, tot, wexc, n0, MID, NY, NX, k0, ky, kx, st);
+    }
     void ex1d_small(const T* R, T* exc, i64 n, i64 k) {
         launch_ex1d_small<T, Op>(R, exc, n, k, st);
     }

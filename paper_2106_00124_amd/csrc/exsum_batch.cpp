@@ -57,6 +57,10 @@ struct ListSink {
     // the single-workgroup kernel for a short last level has no work-list form
     bool small1d_ok(i64) const { return false; }
     void ex1d_small(const T*, T*, i64, i64) {}
+    // weak excluded sums are rejected when the batch is created
+    void total(const T*, i64, void*, T*) {}
+    void weak_exc(const T*, const T*, T*, i64) {}
+    void plane_weak(const T*, T*, const T*, T*, i64, i64, i64, i64, i64, i64, i64) {}
     void push(const Step& s, int kb) { out->push_back(Rec{s, dtype, op, kb}); }
     void bdbs(const T* in, T* o, i64 O, i64 n, i64 I, i64 k) {
         Step s{};
@@ -460,6 +464,8 @@ exs_status exs_batch_create(const exs_job* jobs, int32_t n, const char* tune_cac
     size_t off = 0;
     for (int j = 0; j < n; ++j) {
         exs_status s = validate_job(&b->jobs[j], true);
+        if (s == EXS_OK && (b->jobs[j].mode & EXS_WEAK))
+            s = set_error(EXS_EUNSUPPORTED, "weak excluded sums are not batched");
         if (s != EXS_OK) {
             delete b;
             return set_error(s, "job " + std::to_string(j) + ": " + exs_last_error());

@@ -23,6 +23,15 @@ namespace exs {
 // ---------------------------------------------------------------------------
 struct OpSum {
     template <typename T> static __device__ __forceinline__ T id() { return T(0); }
+    // a - b: + has an inverse (weak excluded sums, total - included)
+    static __device__ __forceinline__ float inverse(float a, float b) { return a - b; }
+    static __device__ __forceinline__ double inverse(double a, double b) { return a - b; }
+    static __device__ __forceinline__ int inverse(int a, int b) {
+        return (int)((unsigned)a - (unsigned)b);
+    }
+    static __device__ __forceinline__ long long inverse(long long a, long long b) {
+        return (long long)((unsigned long long)a - (unsigned long long)b);
+    }
     static __device__ __forceinline__ float apply(float a, float b) { return a + b; }
     static __device__ __forceinline__ double apply(double a, double b) { return a + b; }
     static __device__ __forceinline__ int apply(int a, int b) {
@@ -35,6 +44,8 @@ struct OpSum {
 
 struct OpMax {
     template <typename T> static __device__ __forceinline__ T id();
+    // max has no inverse; never called (weak excluded sums are + only)
+    template <typename T> static __device__ __forceinline__ T inverse(T a, T) { return a; }
     // fp32 max as one v_max_f32.  fmaxf would first quiet signalling NaNs in
     // every operand read from memory (an extra v_max_f32 x, x, x each), which
     // finite inputs do not need and which costs registers in the unrolled

@@ -33,6 +33,17 @@ void launch_worklist(int dtype, int op, int kind, int kb, const void* steps, int
 // generic-path launchers (exsum_kernels.hip)
 template <typename T, class Op>
 void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st);
+// weak excluded sums (+ only): the total of the tensor in two deterministic
+// stages (partials in `parts`, TOT_PARTS 8-byte slots), the fused stream kernel
+// with the total - included epilogue, and the same epilogue as its own pass
+constexpr int TOT_PARTS = 1024;
+template <typename T>
+void launch_total(const T* X, i64 N, void* parts, T* tot, hipStream_t st);
+template <typename T, class Op>
+void launch_plane_weak(const T* X, T* inc, const T* wtot, T* wexc, i64 n0, i64 MID, i64 NY,
+                       i64 NX, i64 k0, i64 ky, i64 kx, hipStream_t st);
+template <typename T>
+void launch_weak_exc(const T* inc, const T* tot, T* exc, i64 N, hipStream_t st);
 // excluded sums of a 1-D tensor of at most 8192 elements in one workgroup
 bool ex1d_small_ok(i64 n);
 template <typename T, class Op>

@@ -283,6 +283,124 @@ void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st
 #undef EXS_BDBS_CASE
 }
 
+// ---------------------------------------------------------------------------
+// Weak excluded sums for + (the "total minus included" route of the paper's
+// BDBSC, Sec. 1 and Sec. 6): the total in FP64 (floats) or wrapping 64-bit
+// integers, in two stages with a fixed order, so it is the same on every run.
+// ---------------------------------------------------------------------------
+template <typename T> struct TotAcc { typedef double type; };
+template <> struct TotAcc<int> { typedef unsigned long long type; };
+template <> struct TotAcc<long long> { typedef unsigned long long type; };
+
+template <typename A>
+__device__ __forceinline__ A block_sum256(A v, A* sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) sh[t] = sh[t] + sh[t + s];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// Stage 1: each workgroup reduces a fixed, grid-strided share of the tensor.
+// 4-byte types with a 16-byte aligned base read 16 bytes per load, four loads
+// in flight, one accumulator per lane component; the tail (N mod 4 elements)
+// goes to workgroup 0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_total_part(const T* __restrict__ X, i64 N,
+                                                    typename TotAcc<T>::type* __restrict__ parts) {
+    typedef typename TotAcc<T>::type A;
+    __shared__ A sh[256];
+    A acc = 0;
+    const i64 stride = (i64)gridDim.x * 256;
+    const i64 t0 = (i64)blockIdx.x * 256 + threadIdx.x;
+    if constexpr (sizeof(T) == 4) {
+        if (((uintptr_t)X & 15) == 0) {
+            const i64 N4 = N >> 2;
+            const uint4* __restrict__ X4 = (const uint4*)X;
+            A a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+            i64 i = t0;
+            for (; i + 3 * stride < N4; i += 4 * stride) {
+                uint4 v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = X4[i + u * stride];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    a0 = a0 + (A)__builtin_bit_cast(T, v[u].x);
+                    a1 = a1 + (A)__builtin_bit_cast(T, v[u].y);
+                    a2 = a2 + (A)__builtin_bit_cast(T, v[u].z);
+                    a3 = a3 + (A)__builtin_bit_cast(T, v[u].w);
+                }
+            }
+            for (; i < N4; i += stride) {
+                const uint4 v = X4[i];
+                a0 = a0 + (A)__builtin_bit_cast(T, v.x);
+                a1 = a1 + (A)__builtin_bit_cast(T, v.y);
+                a2 = a2 + (A)__builtin_bit_cast(T, v.z);
+                a3 = a3 + (A)__builtin_bit_cast(T, v.w);
+            }
+            acc = (a0 + a1) + (a2 + a3);
+            if (blockIdx.x == 0)
+                for (i64 j = (N4 << 2) + threadIdx.x; j < N; j += 256) acc = acc + (A)X[j];
+            const A s = block_sum256<A>(acc, sh);
+            if (threadIdx.x == 0) parts[blockIdx.x] = s;
+            return;
+        }
+    }
+    for (i64 i = t0; i < N; i += stride) acc = acc + (A)X[i];
+    const A s = block_sum256<A>(acc, sh);
+    if (threadIdx.x == 0) parts[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_total_final(const typename TotAcc<T>::type* __restrict__ parts,
+                                                     int nparts, T* __restrict__ tot) {
+    typedef typename TotAcc<T>::type A;
+    __shared__ A sh[256];
+    A acc = 0;
+    for (int i = threadIdx.x; i < nparts; i += 256) acc = acc + parts[i];
+    const A s = block_sum256<A>(acc, sh);
+    if (threadIdx.x == 0) tot[0] = (T)s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_weak_exc(const T* __restrict__ inc,
+                                                  const T* __restrict__ tot, T* __restrict__ exc,
+                                                  i64 N) {
+    const i64 i = gtid();
+    if (i < N) exc[i] = OpSum::inverse(tot[0], inc[i]);
+}
+
+template <typename T>
+void launch_total(const T* X, i64 N, void* parts, T* tot, hipStream_t st) {
+    KTimer timer("k_total", st);
+    typedef typename TotAcc<T>::type A;
+    i64 g = (N + 256 * 64 - 1) / (256 * 64);
+    if (g > TOT_PARTS) g = TOT_PARTS;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL((k_total_part<T>), dim3((unsigned)g), dim3(256), 0, st, X, N, (A*)parts);
+    hipLaunchKernelGGL((k_total_final<T>), dim3(1), dim3(256), 0, st, (const A*)parts, (int)g,
+                       tot);
+}
+
+template <typename T>
+void launch_weak_exc(const T* inc, const T* tot, T* exc, i64 N, hipStream_t st) {
+    KTimer timer("k_weak_exc", st);
+    hipLaunchKernelGGL((k_weak_exc<T>), dim3(grid_for(N)), dim3(256), 0, st, inc, tot, exc, N);
+}
+
+template void launch_total<float>(const float*, i64, void*, float*, hipStream_t);
+template void launch_total<double>(const double*, i64, void*, double*, hipStream_t);
+template void launch_total<int>(const int*, i64, void*, int*, hipStream_t);
+template void launch_total<long long>(const long long*, i64, void*, long long*, hipStream_t);
+template void launch_weak_exc<float>(const float*, const float*, float*, i64, hipStream_t);
+template void launch_weak_exc<double>(const double*, const double*, double*, i64, hipStream_t);
+template void launch_weak_exc<int>(const int*, const int*, int*, i64, hipStream_t);
+template void launch_weak_exc<long long>(const long long*, const long long*, long long*, i64,
+                                         hipStream_t);
+
 template <typename T, class Op>
 void launch_ex1d_small(const T* R, T* exc, i64 n, i64 k, hipStream_t st) {
     KTimer timer("k_ex1d_small", st);

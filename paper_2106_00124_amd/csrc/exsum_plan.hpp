@@ -76,7 +76,8 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
     const T* A = (const T*)job->in_dev;
     T* inc = (job->mode & EXS_INCLUDED) ? (T*)job->inc_out_dev : nullptr;
     T* exc = (job->mode & EXS_EXCLUDED) ? (T*)job->exc_out_dev : nullptr;
-    const bool want_exc = job->mode & EXS_EXCLUDED;
+    const bool weak = job->mode & EXS_WEAK;
+    const bool want_exc = (job->mode & EXS_EXCLUDED) && !weak;  // strong excluded sums
     const bool dry = ar.dry;
     const i64 N = prod(n, 0, d);
     // level 0 streams axis 0 with the fused plane kernel when it applies; it
@@ -98,6 +99,28 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
     T* wb1 = wb_count >= 2 ? ar.take<T>(wb_elems) : nullptr;
 
     sink.level(0);
+    if (weak) {
+        // weak excluded sums for +: total - included (the paper's BDBSC
+        // route, Sec. 1 and Sec. 6), the included sums by BDBS along every
+        // axis; exc doubles as the included buffer when inc is not wanted
+        T* tot = ar.take<T>(1);
+        unsigned long long* parts = ar.take<unsigned long long>(TOT_PARTS);
+        if (!dry) sink.total(A, N, parts, tot);
+        if (fused) {
+            const T* X0 = filter_axes<T>(A, n, k, d, 1, d - 3, wb0, wb1, dry, sink);
+            if (!dry)
+                sink.plane_weak(X0, inc, tot, exc, n[0], prod(n, 1, d - 2), n[d - 2], n[d - 1],
+                                k[0], k[d - 2], k[d - 1]);
+            return EXS_OK;
+        }
+        const T* W = filter_axes<T>(A, n, k, d, 1, d - 1, wb0, wb1, dry, sink);
+        T* incb = inc ? inc : exc;
+        if (!dry) {
+            sink.bdbs(W, incb, 1, n[0], prod(n, 1, d), k[0]);
+            sink.weak_exc(incb, tot, exc, N);
+        }
+        return EXS_OK;
+    }
     if (!want_exc) {
         // included sums only: BDBS along every axis
         if (fused) {

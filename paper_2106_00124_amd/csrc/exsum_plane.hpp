@@ -39,6 +39,8 @@ struct PlaneArgs {
     const void* Trest;  // (M) lower-dimensional excluded sums, or null
     void* exc;          // (n0, M) or null
     void* inc;          // (n0, M) or null
+    const void* wtot;   // weak excluded sums: the total of the tensor (one element)
+    void* wexc;         // weak excluded sums: (n0, M) total minus included, or null
     i64 n0, MID, NY, NX, M, Q;
     int k0, ky, kx;
     i64 tilesY, tilesX, segblocks, nseg;
@@ -135,7 +137,8 @@ __device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, unsigned vof
 // WHOLE: every block of the run is exactly K0B planes (k0 == K0B, n0 a
 // multiple of k0) and K0B / P is even, so each block is a fixed sequence of
 // full rounds; otherwise rounds are sized at run time.
-template <typename T, class Op, int K0B, int KP, bool WHOLE>
+// WEAK: also store total - included (the weak excluded sum, + only).
+template <typename T, class Op, int K0B, int KP, bool WHOLE, bool WEAK>
 __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
     using C = PlaneCfg<KP>;
     constexpr int NT = C::NT, P = C::P, SA = C::SA, SB = C::SB;
@@ -229,6 +232,8 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
     if (t_end > n0) t_end = n0;
 
     const bool do_ex = a.exc != nullptr, do_inc = a.inc != nullptr;
+    T wtot = e;
+    if constexpr (WEAK) wtot = *(const T*)a.wtot;
     T* __restrict__ exc = (T*)a.exc;
     T* __restrict__ inc = (T*)a.inc;
 
@@ -274,19 +279,24 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
                     bstore_nt<T>(ob, mb + (unsigned)r * plane_bytes, Op::apply(tmp[r], S));
                 }
             }
-            if (do_inc) {
+            if (do_inc || WEAK) {
                 // BDBS along axis 0: range suffix in block q-1, range prefix
                 // of block q up to the row before
                 T s = e;
 #pragma unroll
                 for (int r = K0B - 1; r >= 0; --r) { s = Op::apply(w[r], s); tmp[r] = s; }
-                const __amdgpu_buffer_rsrc_t ob = buf(inc + (i64)xb * M, blk_bytes);
+                const __amdgpu_buffer_rsrc_t ob =
+                    do_inc ? buf(inc + (i64)xb * M, blk_bytes) : buf(X, 0u);
+                const __amdgpu_buffer_rsrc_t ow =
+                    WEAK ? buf((T*)a.wexc + (i64)xb * M, blk_bytes) : buf(X, 0u);
                 T p = e;
 #pragma unroll
                 for (int r = 0; r < K0B; ++r) {
                     T val = tmp[r];
                     if (r > 0) { p = Op::apply(p, v[r - 1]); val = Op::apply(val, p); }
-                    bstore_nt<T>(ob, mb + (unsigned)r * plane_bytes, val);
+                    if (do_inc) bstore_nt<T>(ob, mb + (unsigned)r * plane_bytes, val);
+                    if constexpr (WEAK)
+                        bstore_nt<T>(ow, mb + (unsigned)r * plane_bytes, Op::inverse(wtot, val));
                 }
             }
         }
@@ -781,7 +791,7 @@ void launch_plane_bdbs(const T* X, T* W, i64 O, i64 NY, i64 NX, i64 ky, i64 kx, 
     else launch_plane_bdbs_kp<T, Op, 16>(pa, st);
 }
 
-template <typename T, class Op, int K0B, int KP>
+template <typename T, class Op, int K0B, int KP, bool WEAK>
 void launch_plane_kernel(PlaneArgs pa, hipStream_t st) {
     using C = PlaneCfg<KP>;
     const i64 ty = (i64)C::NBY * pa.ky, tx = (i64)C::NBX * pa.kx;
@@ -794,22 +804,29 @@ void launch_plane_kernel(PlaneArgs pa, hipStream_t st) {
     // whole blocks: every block of every run has exactly K0B planes
     if constexpr (K0B % (2 * C::P) == 0) {
         if (pa.k0 == K0B && pa.n0 % K0B == 0) {
-            hipLaunchKernelGGL((k_plane_axis0<T, Op, K0B, KP, true>), dim3((unsigned)grid),
+            hipLaunchKernelGGL((k_plane_axis0<T, Op, K0B, KP, true, WEAK>), dim3((unsigned)grid),
                                dim3(C::NT), 0, st, pa);
             return;
         }
     }
-    hipLaunchKernelGGL((k_plane_axis0<T, Op, K0B, KP, false>), dim3((unsigned)grid), dim3(C::NT),
-                       0, st, pa);
+    hipLaunchKernelGGL((k_plane_axis0<T, Op, K0B, KP, false, WEAK>), dim3((unsigned)grid),
+                       dim3(C::NT), 0, st, pa);
 }
 
-template <typename T, class Op, int K0B>
+template <typename T, class Op, int K0B, bool WEAK>
 void launch_plane_kp(PlaneArgs pa, hipStream_t st) {
     const int km = pa.ky > pa.kx ? pa.ky : pa.kx;
-    if (km <= 2) launch_plane_kernel<T, Op, K0B, 2>(pa, st);
-    else if (km <= 4) launch_plane_kernel<T, Op, K0B, 4>(pa, st);
-    else if (km <= 8) launch_plane_kernel<T, Op, K0B, 8>(pa, st);
-    else launch_plane_kernel<T, Op, K0B, 16>(pa, st);
+    if (km <= 2) launch_plane_kernel<T, Op, K0B, 2, WEAK>(pa, st);
+    else if (km <= 4) launch_plane_kernel<T, Op, K0B, 4, WEAK>(pa, st);
+    else if (km <= 8) launch_plane_kernel<T, Op, K0B, 8, WEAK>(pa, st);
+    else launch_plane_kernel<T, Op, K0B, 16, WEAK>(pa, st);
+}
+
+template <typename T, class Op, bool WEAK>
+void launch_plane_k0(PlaneArgs pa, hipStream_t st) {
+    if (pa.k0 <= 4) launch_plane_kp<T, Op, 4, WEAK>(pa, st);
+    else if (pa.k0 <= 8) launch_plane_kp<T, Op, 8, WEAK>(pa, st);
+    else launch_plane_kp<T, Op, 16, WEAK>(pa, st);
 }
 
 template <typename T, class Op>
@@ -821,9 +838,21 @@ void launch_plane_axis0(const T* X, const T* PX, const T* SX, const T* Trest, T*
     pa.X = X; pa.PX = PX; pa.SX = SX; pa.Trest = Trest; pa.exc = exc; pa.inc = inc;
     pa.n0 = n0; pa.MID = MID; pa.NY = NY; pa.NX = NX; pa.M = MID * NY * NX; pa.Q = Q;
     pa.k0 = (int)k0; pa.ky = (int)ky; pa.kx = (int)kx;
-    if (k0 <= 4) launch_plane_kp<T, Op, 4>(pa, st);
-    else if (k0 <= 8) launch_plane_kp<T, Op, 8>(pa, st);
-    else launch_plane_kp<T, Op, 16>(pa, st);
+    launch_plane_k0<T, Op, false>(pa, st);
+}
+
+// Included sums (into inc, or nowhere) and weak excluded sums total - included
+// (into wexc), + only.
+template <typename T, class Op>
+void launch_plane_weak(const T* X, T* inc, const T* wtot, T* wexc, i64 n0, i64 MID, i64 NY,
+                       i64 NX, i64 k0, i64 ky, i64 kx, hipStream_t st) {
+    KTimer timer("k_plane_axis0", st);
+    PlaneArgs pa{};
+    pa.X = X; pa.inc = inc; pa.wtot = wtot; pa.wexc = wexc;
+    pa.n0 = n0; pa.MID = MID; pa.NY = NY; pa.NX = NX; pa.M = MID * NY * NX;
+    pa.Q = (n0 + k0 - 1) / k0;
+    pa.k0 = (int)k0; pa.ky = (int)ky; pa.kx = (int)kx;
+    launch_plane_k0<T, Op, true>(pa, st);
 }
 
 }  // namespace exs

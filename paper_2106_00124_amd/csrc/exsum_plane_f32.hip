@@ -39,4 +39,6 @@ template void launch_plane_scan<float, OpSum>(const float*, const float*, float*
                                             i64, i64, i64, i64, i64, hipStream_t);
 template void launch_plane_scan<float, OpMax>(const float*, const float*, float*, float*, float*, i64, i64,
                                             i64, i64, i64, i64, i64, hipStream_t);
+template void launch_plane_weak<float, OpSum>(const float*, float*, const float*, float*, i64, i64,
+                                              i64, i64, i64, i64, i64, hipStream_t);
 }  // namespace exs

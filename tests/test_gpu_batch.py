@@ -126,3 +126,12 @@ def test_batch_rejects_invalid_job():
     x = torch.zeros((4, 4), device="cuda")
     with pytest.raises(ExsError):
         P.Batch([(x, (5, 1), "sum", "both")])
+
+
+def test_batch_rejects_weak_jobs():
+    import torch
+    import paper_2106_00124_amd as P
+    from paper_2106_00124_amd import ExsError
+    x = torch.zeros((16, 16), device="cuda")
+    with pytest.raises(ExsError, match="EUNSUPPORTED"):
+        P.Batch([(x, (2, 2), "sum", "weak")])

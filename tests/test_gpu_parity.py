@@ -117,3 +117,43 @@ def test_deterministic(orc):
     i1, e1 = gpu_run(a, (5, 6, 7), "sum")
     i2, e2 = gpu_run(a, (5, 6, 7), "sum")
     assert np.array_equal(i1, i2) and np.array_equal(e1, e2)
+
+
+WEAK_CASES = [
+    ((1000,), (64,)),
+    ((64, 64), (8, 8)),
+    ((13, 70), (4, 9)),
+    ((33, 17, 65), (16, 16, 16)),
+    ((40, 70, 90), (5, 7, 9)),
+    ((16, 8, 64, 64), (8, 8, 4, 4)),
+    ((5, 6, 7, 40, 50), (2, 3, 4, 5, 6)),
+    ((64, 256, 256), (2, 16, 16)),
+    ((70, 40, 50), (33, 5, 6)),
+]
+
+
+@pytest.mark.parametrize("shape,box", WEAK_CASES, ids=lambda v: "x".join(map(str, v)))
+@pytest.mark.parametrize("dtype", ["f32", "f64", "i32", "i64"])
+def test_parity_weak(orc, shape, box, dtype):
+    """Weak excluded sums (total - included, + only) against the oracle; the
+    included output of the same call is the strong path's."""
+    say(f"[weak] shape={shape} box={box} dtype={dtype}")
+    a = make_input(shape, dtype, seed=hash((shape, box, dtype, 7)) % 2**32, op="sum")
+    inc, exc = gpu_run(a, box, "sum", "both_weak")
+    compare_full(orc, a, box, "sum", dtype, inc, exc, what=f"weak {shape} {box} {dtype}")
+    _, exc_only = gpu_run(a, box, "sum", "weak")
+    inc_strong, _ = gpu_run(a, box, "sum", "inc")
+    if dtype in ("i32", "i64"):
+        assert np.array_equal(exc_only, exc)
+        assert np.array_equal(inc, inc_strong)
+    else:
+        compare_full(orc, a, box, "sum", dtype, None, exc_only, what="weak exc only")
+
+
+def test_weak_max_unsupported():
+    import torch
+    import paper_2106_00124_amd as P
+    from paper_2106_00124_amd import ExsError
+    x = torch.zeros((8, 8), device="cuda")
+    with pytest.raises(ExsError, match="EUNSUPPORTED"):
+        P.run(x, (2, 2), "max", "weak")
