@@ -150,6 +150,12 @@ struct EagerSink {
         launch_blockagg<T, Op>(X, Ga, n0, M, k0, Q, st);
     }
     bool small1d_ok(i64 n) const { return ex1d_small_ok(n); }
+    void segtot(const T* Gw, const T* Ga, T* Tw, T* Ta, i64 Q, i64 M, i64 L) {
+        launch_segtot<T, Op>(Gw, Ga, Tw, Ta, Q, M, L, st);
+    }
+    void segexp(const T* Gw, const T* SPX, const T* SSX, T* PX, T* SX, i64 Q, i64 M, i64 L) {
+        launch_segexp<T, Op>(Gw, SPX, SSX, PX, SX, Q, M, L, st);
+    }
     void total(const T* X, i64 N, void* parts, T* tot) { launch_total<T>(X, N, parts, tot, st); }
     void weak_exc(const T* inc, const T* tot, T* exc, i64 N) {
         launch_weak_exc<T>(inc, tot, exc, N, st);

@@ -78,7 +78,7 @@ struct ListSink {
             return;
         }
         const i64 rcb = I == 1 ? rows_blocks(O, n, k, ROWS_MIN_TASKS) : 0;
-        if (I == 1 && rows_tasks(O, n, k, rcb) >= ROWS_MIN_TASKS) {
+        if (I == 1 && O >= ROWS_PER_TASK && rows_tasks(O, n, k, rcb) >= ROWS_MIN_TASKS) {
             // rows of the contiguous axis of a large tensor: wavefront tasks
             // through LDS
             s.kind = SK_BDBSR;
@@ -98,6 +98,33 @@ struct ListSink {
         s.nchunks = (nb + s.cb - 1) / s.cb;
         s.ntasks = cols * s.nchunks;
         push(s, kb);
+    }
+    void segtot(const T* Gw, const T* Ga, T* Tw, T* Ta, i64 Q, i64 M, i64 L) {
+        Step s{};
+        s.kind = SK_SEGTOT;
+        s.in0 = Gw;
+        s.in1 = Ga;
+        s.out0 = Tw;
+        s.out1 = Ta;
+        s.Q = Q;
+        s.I = M;
+        s.cb = L;
+        s.ntasks = ((Q + L - 1) / L) * M;
+        push(s, 1);
+    }
+    void segexp(const T* Gw, const T* SPX, const T* SSX, T* PX, T* SX, i64 Q, i64 M, i64 L) {
+        Step s{};
+        s.kind = SK_SEGEXP;
+        s.in0 = Gw;
+        s.in1 = SPX;
+        s.in2 = SSX;
+        s.out0 = PX;
+        s.out1 = SX;
+        s.Q = Q;
+        s.I = M;
+        s.cb = L;
+        s.ntasks = ((Q + L - 1) / L) * M;
+        push(s, 1);
     }
     void blockagg(const T* X, T* Ga, i64 n0, i64 M, i64 k0, i64 Q) {
         Step s{};

@@ -44,6 +44,12 @@ void launch_plane_weak(const T* X, T* inc, const T* wtot, T* wexc, i64 n0, i64 M
                        i64 NX, i64 k0, i64 ky, i64 kx, hipStream_t st);
 template <typename T>
 void launch_weak_exc(const T* inc, const T* tot, T* exc, i64 N, hipStream_t st);
+// segmented block scans (few points, many blocks)
+template <typename T, class Op>
+void launch_segtot(const T* Gw, const T* Ga, T* Tw, T* Ta, i64 Q, i64 M, i64 L, hipStream_t st);
+template <typename T, class Op>
+void launch_segexp(const T* Gw, const T* SPX, const T* SSX, T* PX, T* SX, i64 Q, i64 M, i64 L,
+                   hipStream_t st);
 // excluded sums of a 1-D tensor of at most 8192 elements in one workgroup
 bool ex1d_small_ok(i64 n);
 template <typename T, class Op>

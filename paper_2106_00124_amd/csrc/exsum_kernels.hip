@@ -170,6 +170,23 @@ __global__ __launch_bounds__(256) void k_blockscan(const T* __restrict__ Gw,
     if (m < M) task_scan<T, Op>(Gw, Ga, PX, SX, R, Q, M, m);
 }
 
+template <typename T, class Op>
+__global__ __launch_bounds__(256) void k_segtot(const T* __restrict__ Gw, const T* __restrict__ Ga,
+                                                T* __restrict__ Tw, T* __restrict__ Ta, i64 Q,
+                                                i64 M, i64 L) {
+    const i64 i = gtid();
+    if (i < ((Q + L - 1) / L) * M) task_segtot<T, Op>(Gw, Ga, Tw, Ta, Q, M, L, i);
+}
+
+template <typename T, class Op>
+__global__ __launch_bounds__(256) void k_segexp(const T* __restrict__ Gw,
+                                                const T* __restrict__ SPX,
+                                                const T* __restrict__ SSX, T* __restrict__ PX,
+                                                T* __restrict__ SX, i64 Q, i64 M, i64 L) {
+    const i64 i = gtid();
+    if (i < ((Q + L - 1) / L) * M) task_segexp<T, Op>(Gw, SPX, SSX, PX, SX, Q, M, L, i);
+}
+
 template <typename T, class Op, int K0B>
 __global__ __launch_bounds__(256) void k_axis0(const T* __restrict__ W, const T* __restrict__ PX,
                                                const T* __restrict__ SX,
@@ -243,7 +260,7 @@ void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st
     }
     const i64 nb = (n + k - 1) / k;
     const i64 rcb = I == 1 ? rows_blocks(O, n, k, ROWS_MIN_TASKS) : 0;
-    if (I == 1 && rows_tasks(O, n, k, rcb) >= ROWS_MIN_TASKS) {
+    if (I == 1 && O >= ROWS_PER_TASK && rows_tasks(O, n, k, rcb) >= ROWS_MIN_TASKS) {
         // rows of the contiguous axis, enough of them to fill the GPU with
         // wavefront tasks: staged through LDS (fewer, coalesced transactions;
         // small tensors keep the one-row-per-lane kernel, which has the
@@ -433,6 +450,21 @@ void launch_blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M
 }
 
 template <typename T, class Op>
+void launch_segtot(const T* Gw, const T* Ga, T* Tw, T* Ta, i64 Q, i64 M, i64 L, hipStream_t st) {
+    KTimer timer("k_segtot", st);
+    hipLaunchKernelGGL((k_segtot<T, Op>), dim3(grid_for(((Q + L - 1) / L) * M)), dim3(256), 0, st,
+                       Gw, Ga, Tw, Ta, Q, M, L);
+}
+
+template <typename T, class Op>
+void launch_segexp(const T* Gw, const T* SPX, const T* SSX, T* PX, T* SX, i64 Q, i64 M, i64 L,
+                   hipStream_t st) {
+    KTimer timer("k_segexp", st);
+    hipLaunchKernelGGL((k_segexp<T, Op>), dim3(grid_for(((Q + L - 1) / L) * M)), dim3(256), 0, st,
+                       Gw, SPX, SSX, PX, SX, Q, M, L);
+}
+
+template <typename T, class Op>
 void launch_axis0(const T* W, const T* PX, const T* SX, const T* Trest, T* exc, T* inc, i64 n0,
                   i64 M, i64 k0, i64 Q, hipStream_t st) {
     const int kb = bucket_for(k0);
@@ -475,6 +507,9 @@ void launch_fill(void* out, i64 count, int dtype, int kind, uint64_t seed, i64 l
 
 #define EXS_INSTANTIATE(T, OP)                                                                 \
     template void launch_ex1d_small<T, OP>(const T*, T*, i64, i64, hipStream_t);               \
+    template void launch_segtot<T, OP>(const T*, const T*, T*, T*, i64, i64, i64, hipStream_t); \
+    template void launch_segexp<T, OP>(const T*, const T*, const T*, T*, T*, i64, i64, i64,     \
+                                       hipStream_t);                                           \
     template void launch_bdbs<T, OP>(const T*, T*, i64, i64, i64, i64, hipStream_t);           \
     template void launch_blockagg<T, OP>(const T*, T*, i64, i64, i64, i64, hipStream_t);       \
     template void launch_blockscan<T, OP>(const T*, const T*, T*, T*, T*, i64, i64,            \

@@ -68,6 +68,29 @@ static const T* filter_axes(const T* src, const i64* n, const i64* k, int d, int
     return cur;
 }
 
+// Block scans of a level (PX, SX over the Q blocks of each of the M points,
+// and R = op of Ga over all blocks).  With few points and many blocks the
+// direct scan is a long serial walk per point; then the blocks are cut into
+// segments of L, the segment totals are scanned the same way (recursively),
+// and the segments are expanded in parallel.
+template <typename T, class Sink>
+static void emit_blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M, Arena& ar,
+                           bool dry, Sink& sink) {
+    constexpr i64 L = 64;
+    if (M >= 16384 || Q <= L) {
+        if (!dry) sink.blockscan(Gw, Ga, PX, SX, R, Q, M);
+        return;
+    }
+    const i64 S = (Q + L - 1) / L;
+    T* Tw = ar.take<T>(S * M);
+    T* Ta = ar.take<T>(S * M);
+    T* SPX = ar.take<T>(S * M);
+    T* SSX = ar.take<T>(S * M);
+    if (!dry) sink.segtot(Gw, Ga, Tw, Ta, Q, M, L);
+    emit_blockscan<T>(Tw, Ta, SPX, SSX, R, S, M, ar, dry, sink);
+    if (!dry) sink.segexp(Gw, SPX, SSX, PX, SX, Q, M, L);
+}
+
 template <typename T, class Sink>
 static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
     const int d = job->d;
@@ -202,7 +225,7 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
         } else {
             Gw = filter_axes<T>(Ga, gn, gk, dj, 1, dj - 1, gb0, gb1, dry, sink);
         }
-        if (!dry) sink.blockscan(Gw, Ga, PX[j], SX[j], R[j + 1], Q[j], M[j]);
+        emit_blockscan<T>(Gw, Ga, PX[j], SX[j], R[j + 1], Q[j], M[j], ar, dry, sink);
     }
     // bottom-up: stream the first axis of each level, adding the level below
     for (int j = d - 1; j >= 0; --j) {

@@ -22,7 +22,9 @@ enum StepKind : int {
     SK_AX0 = 4,    // axis-0 stream: excluded and/or included sums (k0 <= 64)
     SK_EX2 = 5,    // axis-0 excluded part, two sweeps (any k0)
     SK_BDBSR = 6,  // BDBS along the contiguous axis through LDS (k <= 64; wavefront tasks)
-    SK_NKINDS = 7
+    SK_SEGTOT = 7, // block scans over many blocks for few points: segment totals
+    SK_SEGEXP = 8, // ... and the expansion of the scanned segment totals
+    SK_NKINDS = 9
 };
 
 // One step of the generic path.  Pointers are device pointers; the meaning
@@ -125,6 +127,49 @@ __device__ __forceinline__ void task_scan(const T* __restrict__ Gw, const T* __r
         s = Op::apply(Gw[q * M + m], s);
     }
     if (R) R[m] = r;
+}
+
+// Block scans over Q blocks when there are few points m (the direct scan is
+// one serial walk over all Q blocks per point): segments of L blocks.
+// Segment totals, task (s, m): Tw[s, m] = op of Gw[q, m], Ta[s, m] = op of
+// Ga[q, m] over the segment's blocks q.
+template <typename T, class Op>
+__device__ __forceinline__ void task_segtot(const T* __restrict__ Gw, const T* __restrict__ Ga,
+                                            T* __restrict__ Tw, T* __restrict__ Ta, i64 Q, i64 M,
+                                            i64 L, i64 idx) {
+    const i64 m = idx % M, sg = idx / M;
+    const i64 q0 = sg * L, q1 = q0 + L < Q ? q0 + L : Q;
+    const T e = Op::template id<T>();
+    T w = e, g = e;
+#pragma unroll 8
+    for (i64 q = q0; q < q1; ++q) {
+        w = Op::apply(w, Gw[q * M + m]);
+        g = Op::apply(g, Ga[q * M + m]);
+    }
+    Tw[idx] = w;
+    Ta[idx] = g;
+}
+
+// Expansion, task (s, m): from the exclusive prefix SPX[s, m] and suffix
+// SSX[s, m] of the segment totals, PX[q, m] and SX[q, m] of the segment's blocks.
+template <typename T, class Op>
+__device__ __forceinline__ void task_segexp(const T* __restrict__ Gw, const T* __restrict__ SPX,
+                                            const T* __restrict__ SSX, T* __restrict__ PX,
+                                            T* __restrict__ SX, i64 Q, i64 M, i64 L, i64 idx) {
+    const i64 m = idx % M, sg = idx / M;
+    const i64 q0 = sg * L, q1 = q0 + L < Q ? q0 + L : Q;
+    T p = SPX[idx];
+#pragma unroll 8
+    for (i64 q = q0; q < q1; ++q) {
+        PX[q * M + m] = p;
+        p = Op::apply(p, Gw[q * M + m]);
+    }
+    T s = SSX[idx];
+#pragma unroll 8
+    for (i64 q = q1 - 1; q >= q0; --q) {
+        SX[q * M + m] = s;
+        s = Op::apply(Gw[q * M + m], s);
+    }
 }
 
 // Axis-0 stream (generic path): task = (run, m), m fastest; the task owns
@@ -351,6 +396,12 @@ __device__ __forceinline__ void run_task(const Step& s, i64 i) {
     else if constexpr (KIND == SK_SCAN)
         task_scan<T, Op>((const T*)s.in0, (const T*)s.in1, (T*)s.out0, (T*)s.out1, (T*)s.out2,
                          s.Q, s.I, i);
+    else if constexpr (KIND == SK_SEGTOT)
+        task_segtot<T, Op>((const T*)s.in0, (const T*)s.in1, (T*)s.out0, (T*)s.out1, s.Q, s.I,
+                           s.cb, i);
+    else if constexpr (KIND == SK_SEGEXP)
+        task_segexp<T, Op>((const T*)s.in0, (const T*)s.in1, (const T*)s.in2, (T*)s.out0,
+                           (T*)s.out1, s.Q, s.I, s.cb, i);
     else if constexpr (KIND == SK_AX0)
         task_axis0<T, Op, KB>((const T*)s.in0, (const T*)s.in1, (const T*)s.in2, (const T*)s.in3,
                               (T*)s.out0, (T*)s.out1, s.n, s.I, s.k, s.Q, s.cb, i);

@@ -90,6 +90,8 @@ static void launch_kind(int kind, int kb, const Step* steps, int nsteps, i64 tot
         case SK_BDBS2: launch_kb<T, Op, SK_BDBS2>(kb, steps, nsteps, total, grid, st); break;
         case SK_AGG: launch_kb<T, Op, SK_AGG>(kb, steps, nsteps, total, grid, st); break;
         case SK_SCAN: launch_kb<T, Op, SK_SCAN>(kb, steps, nsteps, total, grid, st); break;
+        case SK_SEGTOT: launch_kb<T, Op, SK_SEGTOT>(kb, steps, nsteps, total, grid, st); break;
+        case SK_SEGEXP: launch_kb<T, Op, SK_SEGEXP>(kb, steps, nsteps, total, grid, st); break;
         case SK_AX0: launch_kb<T, Op, SK_AX0>(kb, steps, nsteps, total, grid, st); break;
         case SK_EX2: launch_kb<T, Op, SK_EX2>(kb, steps, nsteps, total, grid, st); break;
     }

@@ -32,6 +32,9 @@ def _mixed_items(seed, count):
     # many rows along the contiguous axis (LDS-staged row tasks)
     items.append(((40000, 70), (3, 9), "f32", "sum", "both", 13))
     items.append(((300, 200, 64), (5, 4, 33), "i32", "max", "both", 14))
+    # many blocks for few points (segmented block scans)
+    items.append(((20000, 5), (3, 2), "f32", "sum", "both", 15))
+    items.append(((60000,), (2,), "i32", "max", "exc", 16))
     return items
 
 

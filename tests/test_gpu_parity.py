@@ -26,6 +26,9 @@ CASES = [
     ((6, 5, 4, 3, 2), (3, 2, 4, 1, 2)),
     ((3, 2, 3, 2, 3, 2), (2, 2, 1, 2, 3, 1)),
     ((2, 2, 2, 2, 2, 2, 2, 3), (1, 2, 2, 1, 2, 2, 1, 2)),
+    # many blocks along an axis with few points (segmented block scans)
+    ((300000,), (3,)),
+    ((50000, 3), (2, 2)),
     # a last level longer than the one-workgroup kernel takes
     ((3, 9000), (2, 5)),
     ((2, 3, 8193), (1, 2, 100)),
