@@ -4,9 +4,16 @@
 
 namespace exs {
 
+// Share of the tiles' thread slots that hold a point of the plane: tiny
+// planes leave most of a 32 x 32 tile idle, and the generic passes do better.
+static double plane_fill(i64 NY, i64 NX, i64 ky, i64 kx) {
+    return (double)(NY * NX) / ((double)plane_tiles(NY, NX, ky, kx) * 1024.0);
+}
+
 bool plane_eligible(int d, const i64* n, const i64* k, int es) {
     if (d < 3 || es != 4) return false;
     if (k[0] > 16 || k[d - 2] > 16 || k[d - 1] > 16) return false;
+    if (plane_fill(n[d - 2], n[d - 1], k[d - 2], k[d - 1]) < 0.25) return false;
     // plane and block indices are 32-bit inside the kernel
     if (n[0] + 64 >= ((i64)1 << 31)) return false;
     if (n[d - 2] * n[d - 1] >= ((i64)1 << 31)) return false;
@@ -22,7 +29,8 @@ i64 plane_axis0_run_blocks(i64 Q, i64 MID, i64 NY, i64 NX, i64 ky, i64 kx) {
 }
 
 bool plane2_eligible(i64 NY, i64 NX, i64 ky, i64 kx, int es) {
-    return es == 4 && ky <= 16 && kx <= 16 && NY * NX * es < ((i64)1 << 31);
+    return es == 4 && ky <= 16 && kx <= 16 && NY * NX * es < ((i64)1 << 31) &&
+           plane_fill(NY, NX, ky, kx) >= 0.25;
 }
 
 template void launch_plane_axis0<float, OpSum>(const float*, const float*, const float*,
