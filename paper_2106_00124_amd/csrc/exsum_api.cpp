@@ -79,6 +79,10 @@ exs_status validate_job(const exs_job* job, bool check_ptrs) {
     if (!job->in_dev) return set_error(EXS_EINVAL, "in_dev is NULL");
     if (want_inc && !job->inc_out_dev) return set_error(EXS_EINVAL, "inc_out_dev is NULL");
     if (want_exc && !job->exc_out_dev) return set_error(EXS_EINVAL, "exc_out_dev is NULL");
+    const uintptr_t es = (uintptr_t)dtype_size(job->dtype);
+    if ((uintptr_t)job->in_dev % es || (want_inc && (uintptr_t)job->inc_out_dev % es) ||
+        (want_exc && (uintptr_t)job->exc_out_dev % es))
+        return set_error(EXS_EINVAL, "tensors must be aligned to their element size");
     const uintptr_t bytes = (uintptr_t)(N * (__int128)dtype_size(job->dtype));
     auto overlap = [bytes](const void* a, const void* b) {
         const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
