@@ -154,6 +154,14 @@ struct EagerSink {
         launch_blockagg<T, Op>(X, Ga, n0, M, k0, Q, st);
     }
     bool small1d_ok(i64 n) const { return ex1d_small_ok(n); }
+    bool row_ok(i64 n0, i64 NX, i64 k0, i64 kx) const {
+        return sizeof(T) == 4 && row_eligible(n0, NX, k0, kx, (int)sizeof(T));
+    }
+    void row_axis0(const T* X, const T* PX, const T* SX, const T* Trest, T* exc, T* inc, i64 n0,
+                   i64 NX, i64 k0, i64 kx, i64 Q) {
+        if constexpr (sizeof(T) == 4)
+            launch_row_axis0<T, Op>(X, PX, SX, Trest, exc, inc, n0, NX, k0, kx, Q, st);
+    }
     void segtot(const T* Gw, const T* Ga, T* Tw, T* Ta, i64 Q, i64 M, i64 L) {
         launch_segtot<T, Op>(Gw, Ga, Tw, Ta, Q, M, L, st);
     }

@@ -54,6 +54,9 @@ struct ListSink {
     TuneCfg cfg;
     bool fused_ok = false;
     void level(int) {}
+    // the fused 2-D stream has no work-list form
+    bool row_ok(i64, i64, i64, i64) const { return false; }
+    void row_axis0(const T*, const T*, const T*, const T*, T*, T*, i64, i64, i64, i64, i64) {}
     // the single-workgroup kernel for a short last level has no work-list form
     bool small1d_ok(i64) const { return false; }
     void ex1d_small(const T*, T*, i64, i64) {}

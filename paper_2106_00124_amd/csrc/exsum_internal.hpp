@@ -44,6 +44,11 @@ void launch_plane_weak(const T* X, T* inc, const T* wtot, T* wexc, i64 n0, i64 M
                        i64 NX, i64 k0, i64 ky, i64 kx, hipStream_t st);
 template <typename T>
 void launch_weak_exc(const T* inc, const T* tot, T* exc, i64 N, hipStream_t st);
+// fused 2-D streaming kernel (exsum_row.hpp)
+bool row_eligible(i64 n0, i64 NX, i64 k0, i64 kx, int es);
+template <typename T, class Op>
+void launch_row_axis0(const T* X, const T* PX, const T* SX, const T* Trest, T* exc, T* inc, i64 n0,
+                      i64 NX, i64 k0, i64 kx, i64 Q, hipStream_t st);
 // segmented block scans (few points, many blocks)
 template <typename T, class Op>
 void launch_segtot(const T* Gw, const T* Ga, T* Tw, T* Ta, i64 Q, i64 M, i64 L, hipStream_t st);

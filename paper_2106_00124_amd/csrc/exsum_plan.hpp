@@ -154,6 +154,12 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
                                  (n[0] + k[0] - 1) / k[0]);
             return EXS_OK;
         }
+        if (d == 2 && sink.row_ok(n[0], n[1], k[0], k[1])) {
+            if (!dry)
+                sink.row_axis0(A, nullptr, nullptr, nullptr, nullptr, inc, n[0], n[1], k[0], k[1],
+                               (n[0] + k[0] - 1) / k[0]);
+            return EXS_OK;
+        }
         const T* W = filter_axes<T>(A, n, k, d, 1, d - 1, wb0, wb1, dry, sink);
         if (!dry) sink.bdbs(W, inc, 1, n[0], prod(n, 1, d), k[0]);
         return EXS_OK;
@@ -243,6 +249,13 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
             if (!dry)
                 sink.plane_axis0(X0, PX[0], SX[0], Trest, exc, inc, n[0], prod(n, 1, d - 2),
                                  n[d - 2], n[d - 1], k[0], k[d - 2], k[d - 1], Q[0]);
+            continue;
+        }
+        if (dj == 2 && sink.row_ok(n[j], n[j + 1], k[j], k[j + 1])) {
+            // a 2-D level: the row box-sums and the axis stream in one pass
+            if (!dry)
+                sink.row_axis0(src, PX[j], SX[j], Trest, out, j == 0 ? inc : nullptr, n[j],
+                               n[j + 1], k[j], k[j + 1], Q[j]);
             continue;
         }
         const T* W = filter_axes<T>(src, n + j, k + j, dj, 1, dj - 1, wb0, wb1, dry, sink);

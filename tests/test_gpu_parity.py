@@ -26,6 +26,11 @@ CASES = [
     ((6, 5, 4, 3, 2), (3, 2, 4, 1, 2)),
     ((3, 2, 3, 2, 3, 2), (2, 2, 1, 2, 3, 1)),
     ((2, 2, 2, 2, 2, 2, 2, 3), (1, 2, 2, 1, 2, 2, 1, 2)),
+    # 2-D tensors through the fused row stream: ragged rows and blocks, runs
+    ((1000, 777), (7, 13)),
+    ((200, 4096), (16, 16)),
+    ((33, 300), (16, 3)),
+    ((517, 64), (2, 1)),
     # many blocks along an axis with few points (segmented block scans)
     ((300000,), (3,)),
     ((50000, 3), (2, 2)),
