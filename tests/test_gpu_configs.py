@@ -74,3 +74,37 @@ def test_config_d5_32_f32(orc):
 
 def test_config_d4_128x128x64x64_i32(orc):
     _check_config(orc, "d4_128x128x64x64_i32", direct_points=64)
+
+
+@pytest.mark.parametrize("shape,box", [
+    ((64, 4096, 4096), (16, 16, 16)),   # 2^30 elements through the fused plane kernel
+    ((3, 715827883), (2, 7)),           # more than 2^31 elements (64-bit indexing)
+], ids=["2^30_plane", "over_2^31"])
+def test_max_size_closed_form(shape, box):
+    """All-ones int32 tensors at the largest sizes: included sums have the
+    closed form prod_i min(k_i, n_i - x_i) and excluded sums N - included
+    (two's-complement wrapping), checked on every cell (on the device) and at
+    sampled cells (on the host)."""
+    import torch
+    import paper_2106_00124_amd as P
+    say(f"[max size] {shape} {box}")
+    x = torch.ones(shape, dtype=torch.int32, device="cuda")
+    inc, exc = P.run(x, box, "sum", "both")
+    torch.cuda.synchronize()
+    N = int(np.prod(shape))
+    wrapN = np.int64(N).astype(np.int32)   # N mod 2^32 as int32
+    # every cell: inc + exc == N (mod 2^32), via wrapping int32 addition
+    assert bool(torch.all(inc + exc == int(wrapN)).item())
+    del x
+    # sampled cells against the closed form
+    rng = np.random.default_rng(5)
+    flat = np.concatenate([rng.integers(0, N, 256), [0, N - 1]])
+    coords = np.array(np.unravel_index(flat, shape)).T
+    ref = np.ones(len(flat), dtype=np.int64)
+    for i, (n, k) in enumerate(zip(shape, box)):
+        ref *= np.minimum(k, n - coords[:, i])
+    idx = torch.from_numpy(flat).cuda()
+    got_inc = inc.reshape(-1)[idx].cpu().numpy().astype(np.int64)
+    got_exc = exc.reshape(-1)[idx].cpu().numpy()
+    assert np.array_equal(got_inc, ref)
+    assert np.array_equal(got_exc, (N - ref).astype(np.int64).astype(np.int32))
