@@ -154,6 +154,10 @@ struct EagerSink {
         launch_blockagg<T, Op>(X, Ga, n0, M, k0, Q, st);
     }
     bool small1d_ok(i64 n) const { return ex1d_small_ok(n); }
+    bool tail_ok(i64 Q, i64 n, i64 k) const { return sizeof(T) == 4 && tail_scan_ok(Q, n, k); }
+    void tail_scan(const T* A1, T* PX, T* SX, T* exc2, i64 Q, i64 n, i64 k, i64 pxe) {
+        if constexpr (sizeof(T) == 4) launch_tail_scan<T, Op>(A1, PX, SX, exc2, Q, n, k, pxe, st);
+    }
     bool row_ok(i64 n0, i64 NX, i64 k0, i64 kx) const {
         return sizeof(T) == 4 && row_eligible(n0, NX, k0, kx, (int)sizeof(T));
     }
@@ -194,10 +198,10 @@ struct EagerSink {
             launch_plane_axis0<T, Op>(X, PX, SX, Trest, exc, inc, n0, MID, NY, NX, k0, ky, kx, Q,
                                       st);
     }
-    void plane_scan(const T* G, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 MID, i64 NY, i64 NX,
-                    i64 ky, i64 kx, i64 pxe) {
+    void plane_scan(const T* G, const T* Ga, T* PX, T* SX, T* R, T* A1, i64 Q, i64 MID, i64 NY,
+                    i64 NX, i64 ky, i64 kx, i64 pxe) {
         if constexpr (sizeof(T) == 4)
-            launch_plane_scan<T, Op>(G, Ga, PX, SX, R, Q, MID, NY, NX, ky, kx, pxe, st);
+            launch_plane_scan<T, Op>(G, Ga, PX, SX, R, A1, Q, MID, NY, NX, ky, kx, pxe, st);
     }
     void plane_bdbs(const T* X, T* W, i64 O, i64 NY, i64 NX, i64 ky, i64 kx) {
         if constexpr (sizeof(T) == 4) launch_plane_bdbs<T, Op>(X, W, O, NY, NX, ky, kx, st);

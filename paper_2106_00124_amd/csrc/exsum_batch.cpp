@@ -196,7 +196,9 @@ struct ListSink {
     void plane_axis0(const T*, const T*, const T*, const T*, T*, T*, i64, i64, i64, i64, i64, i64,
                      i64, i64) {}
     void plane_bdbs(const T*, T*, i64, i64, i64, i64, i64) {}
-    void plane_scan(const T*, const T*, T*, T*, T*, i64, i64, i64, i64, i64, i64, i64) {}
+    void plane_scan(const T*, const T*, T*, T*, T*, T*, i64, i64, i64, i64, i64, i64, i64) {}
+    bool tail_ok(i64, i64, i64) const { return false; }
+    void tail_scan(const T*, T*, T*, T*, i64, i64, i64, i64) {}
 };
 
 template <typename T, class Op>

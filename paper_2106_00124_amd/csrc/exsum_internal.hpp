@@ -46,6 +46,9 @@ template <typename T>
 void launch_weak_exc(const T* inc, const T* tot, T* exc, i64 N, hipStream_t st);
 // fused 2-D streaming kernel (exsum_row.hpp)
 bool row_eligible(i64 n0, i64 NX, i64 k0, i64 kx, int es);
+// blocks of axis 0 per run of the 2-D streaming kernel (it reads the block
+// prefix only where its runs start)
+i64 row_axis0_run_blocks(i64 Q, i64 NX, i64 kx);
 template <typename T, class Op>
 void launch_row_axis0(const T* X, const T* PX, const T* SX, const T* Trest, T* exc, T* inc, i64 n0,
                       i64 NX, i64 k0, i64 kx, i64 Q, hipStream_t st);
@@ -76,8 +79,14 @@ template <typename T, class Op>
 void launch_plane_bdbs(const T* X, T* W, i64 O, i64 NY, i64 NX, i64 ky, i64 kx, hipStream_t st);
 bool plane2_eligible(i64 NY, i64 NX, i64 ky, i64 kx, int es);
 template <typename T, class Op>
-void launch_plane_scan(const T* G, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 MID, i64 NY,
-                       i64 NX, i64 ky, i64 kx, i64 pxe, hipStream_t st);
+void launch_plane_scan(const T* G, const T* Ga, T* PX, T* SX, T* R, T* A1, i64 Q, i64 MID,
+                       i64 NY, i64 NX, i64 ky, i64 kx, i64 pxe, hipStream_t st);
+// the last two levels of a rank-3 tensor from its level-1 block aggregates
+// (Q x n table, 4-byte elements) in one workgroup
+bool tail_scan_ok(i64 Q, i64 n, i64 k);
+template <typename T, class Op>
+void launch_tail_scan(const T* A1, T* PX, T* SX, T* exc2, i64 Q, i64 n, i64 k, i64 pxe,
+                      hipStream_t st);
 // blocks of axis 0 per run of the level-0 streaming kernel (the runs start
 // at multiples of it: the only blocks whose prefix it reads)
 i64 plane_axis0_run_blocks(i64 Q, i64 MID, i64 NY, i64 NX, i64 ky, i64 kx);

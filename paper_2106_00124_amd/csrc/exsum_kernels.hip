@@ -16,6 +16,9 @@
 //                   lower-dimensional excluded sum (Sec. 5, "Adding in the
 //                   Contribution").
 //   k_ex1d_2sweep   the axis-0 excluded part for boxes longer than 64.
+//   k_ex1d_small    the last (1-D) level in one workgroup.
+//   k_tail_scan     the last two levels of a rank-3 tensor in one workgroup,
+//                   from the level-1 block aggregates.
 //   k_fill          counter-based input generator (workload support).
 #include "exsum_internal.hpp"
 #include "exsum_tasks.hpp"
@@ -97,6 +100,156 @@ __global__ __launch_bounds__(1024) void k_ex1d_small(const T* __restrict__ R, T*
         const T lo = x >= 1 ? pre[x - 1] : e;
         const T hi = x + k < n ? suf[x + k] : e;
         exc[x] = Op::apply(lo, hi);
+    }
+}
+
+// Scans of 64 lanes: inclusive prefix (toward higher lanes) and inclusive
+// suffix (toward lower lanes) of one value per lane.
+template <typename T, class Op>
+__device__ __forceinline__ T wave_prefix(T v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T o = __shfl_up(v, off, 64);
+        if (lane >= off) v = Op::apply(o, v);
+    }
+    return v;
+}
+template <typename T, class Op>
+__device__ __forceinline__ T wave_suffix(T v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T o = __shfl_down(v, off, 64);
+        if (lane + off < 64) v = Op::apply(v, o);
+    }
+    return v;
+}
+
+// The last two levels of a rank-3 tensor in one workgroup, from the level-1
+// block aggregates A1 (Q blocks of k0 rows of R_1, n columns; written by the
+// level-0 scan kernel, so R_1 itself is not read here):
+//   R_2[x]  = op of A1 over the blocks (the reduction over axis 1, Sec. 5);
+//   Gw      = A1 box-summed along the columns (BDBS, Sec. 3; the box-sum
+//             along the columns and the reduction over a block commute);
+//   PX, SX  = exclusive prefix / suffix of Gw over the blocks (PX only for
+//             blocks q with q % pxe == 0, where the level-1 stream starts);
+//   exc2[x] = prefix of R_2 before x op suffix from x + k (the 1-D level).
+// It stands for a box-sum pass, a block-aggregate pass and a block-scan pass
+// over R_1, and the 1-D level's own kernel.  The table's rows have an odd
+// pitch, so the lanes of a wave (consecutive rows, one block) hit distinct
+// LDS banks.
+constexpr int TAIL_THREADS = 1024, TAIL_TABLE = 16416, TAIL_N = 4096;
+constexpr int TAIL_PER = TAIL_N / TAIL_THREADS;
+
+template <typename T, class Op>
+__global__ __launch_bounds__(1024) void k_tail_scan(const T* __restrict__ A1, T* __restrict__ PX,
+                                                    T* __restrict__ SX, T* __restrict__ exc2,
+                                                    int Q, int n, int k, int pxe) {
+    __shared__ T tab[TAIL_TABLE];
+    __shared__ T pre[TAIL_N];
+    __shared__ T suf[TAIL_N];
+    __shared__ T wt[2][TAIL_THREADS / 64];
+    const T e = Op::template id<T>();
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int QN = Q * n, pitch = n | 1;
+    for (int i = t; i < QN; i += TAIL_THREADS) tab[(i / n) * pitch + i % n] = A1[i];
+    __syncthreads();
+    for (int x = t; x < n; x += TAIL_THREADS) {
+        T r = e;
+        for (int q = 0; q < Q; ++q) r = Op::apply(r, tab[q * pitch + x]);
+        pre[x] = r;
+    }
+    // BDBS of every row in place, TAIL_THREADS (row, block) tasks at a time,
+    // rows fastest: a task reads its block and the next one before the
+    // barrier and writes its own block after it, and the task of the block
+    // before comes in the same or an earlier batch, so every block is read raw
+    const int nb = (n + k - 1) / k;
+    const int tasks = Q * nb;
+    for (int c0 = 0; c0 < tasks; c0 += TAIL_THREADS) {
+        const int task = c0 + t;
+        const bool live = task < tasks;
+        const int q = live ? task % Q : 0, b = live ? task / Q : 0;
+        T* row = tab + q * pitch;
+        const int xb = b * k;
+        T o[16];
+        if (live) {
+            // suffix within block b
+            T s = e;
+#pragma unroll
+            for (int r = 15; r >= 0; --r) {
+                if (r < k && xb + r < n) s = Op::apply(row[xb + r], s);
+                o[r] = s;
+            }
+            // prefix within block b + 1 (identity where it is past the row)
+            T p = e;
+#pragma unroll
+            for (int r = 1; r < 16; ++r) {
+                const int y = xb + k + r - 1;
+                if (r < k && y < n) p = Op::apply(p, row[y]);
+                o[r] = Op::apply(o[r], p);
+            }
+        }
+        __syncthreads();
+        if (live) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (r < k && xb + r < n) row[xb + r] = o[r];
+        }
+        __syncthreads();
+    }
+    // the block prefixes of column j, then (j >= n) the suffixes of column j - n
+    for (int j = t; j < 2 * n; j += TAIL_THREADS) {
+        if (j < n) {
+            T pf = e;
+            for (int q = 0; q < Q; ++q) {
+                if (q % pxe == 0) PX[(i64)q * n + j] = pf;
+                pf = Op::apply(pf, tab[q * pitch + j]);
+            }
+        } else {
+            const int x = j - n;
+            T sf = e;
+            for (int q = Q - 1; q >= 0; --q) {
+                SX[(i64)q * n + x] = sf;
+                sf = Op::apply(tab[q * pitch + x], sf);
+            }
+        }
+    }
+    // the 1-D level: each thread scans its TAIL_PER consecutive elements of
+    // R_2, lane scans and a pass over the wave totals give the offsets
+    __syncthreads();
+    const int b0 = t * TAIL_PER;
+    T v[TAIL_PER];
+#pragma unroll
+    for (int r = 0; r < TAIL_PER; ++r) v[r] = b0 + r < n ? pre[b0 + r] : e;
+    T run = e;
+#pragma unroll
+    for (int r = 0; r < TAIL_PER; ++r) run = Op::apply(run, v[r]);
+    const T ip = wave_prefix<T, Op>(run, lane);
+    const T is = wave_suffix<T, Op>(run, lane);
+    if (lane == 63) wt[0][wv] = ip;
+    if (lane == 0) wt[1][wv] = is;
+    __syncthreads();
+    T lo = e, hi = e;
+    for (int w = 0; w < wv; ++w) lo = Op::apply(lo, wt[0][w]);
+    for (int w = TAIL_THREADS / 64 - 1; w > wv; --w) hi = Op::apply(wt[1][w], hi);
+    T before = __shfl_up(ip, 1, 64);
+    before = lane > 0 ? Op::apply(lo, before) : lo;
+    T after = __shfl_down(is, 1, 64);
+    after = lane < 63 ? Op::apply(after, hi) : hi;
+#pragma unroll
+    for (int r = 0; r < TAIL_PER; ++r) {
+        before = Op::apply(before, v[r]);
+        if (b0 + r < n) pre[b0 + r] = before;
+    }
+#pragma unroll
+    for (int r = TAIL_PER - 1; r >= 0; --r) {
+        after = Op::apply(v[r], after);
+        if (b0 + r < n) suf[b0 + r] = after;
+    }
+    __syncthreads();
+    for (int x = t; x < n; x += TAIL_THREADS) {
+        const T l = x >= 1 ? pre[x - 1] : e;
+        const T h = x + k < n ? suf[x + k] : e;
+        exc2[x] = Op::apply(l, h);
     }
 }
 
@@ -426,6 +579,27 @@ void launch_ex1d_small(const T* R, T* exc, i64 n, i64 k, hipStream_t st) {
 }
 
 bool ex1d_small_ok(i64 n) { return n <= EX1_MAX; }
+
+bool tail_scan_ok(i64 Q, i64 n, i64 k) {
+    return Q * (n | 1) <= TAIL_TABLE && n <= TAIL_N && k <= 16;
+}
+
+template <typename T, class Op>
+void launch_tail_scan(const T* A1, T* PX, T* SX, T* exc2, i64 Q, i64 n, i64 k, i64 pxe,
+                      hipStream_t st) {
+    static_assert(sizeof(T) == 4, "the tables are sized for 4-byte elements");
+    KTimer timer("k_tail_scan", st);
+    hipLaunchKernelGGL((k_tail_scan<T, Op>), dim3(1), dim3(TAIL_THREADS), 0, st, A1, PX, SX, exc2,
+                       (int)Q, (int)n, (int)k, (int)pxe);
+}
+template void launch_tail_scan<float, OpSum>(const float*, float*, float*, float*, i64, i64, i64,
+                                             i64, hipStream_t);
+template void launch_tail_scan<float, OpMax>(const float*, float*, float*, float*, i64, i64, i64,
+                                             i64, hipStream_t);
+template void launch_tail_scan<int, OpSum>(const int*, int*, int*, int*, i64, i64, i64, i64,
+                                           hipStream_t);
+template void launch_tail_scan<int, OpMax>(const int*, int*, int*, int*, i64, i64, i64, i64,
+                                           hipStream_t);
 
 template <typename T, class Op>
 void launch_blockagg(const T* X, T* Ga, i64 n0, i64 M, i64 k0, i64 Q, hipStream_t st) {

@@ -194,6 +194,15 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
     // the last level is 1-D; when short, one workgroup computes its excluded
     // sums directly from R_{d-1} (no block passes)
     const bool last_small = d >= 2 && sink.small1d_ok(n[d - 1]);
+    // rank 3 with the one-pass level-0 scan: that pass also reduces R_1 over
+    // the level-1 blocks (its tiles hold whole blocks), and when that table
+    // is small one workgroup finishes levels 1 and 2 from it (box-sums, block
+    // scans, the 1-D level); only the level-1 stream then reads R_1
+    const bool scan0 = fused && Q[0] <= 32 &&
+                       plane2_eligible(n[d - 2], n[d - 1], k[d - 2], k[d - 1], (int)sizeof(T));
+    const bool tail = scan0 && d == 3 && sink.row_ok(n[1], n[2], k[1], k[2]) &&
+                      sink.tail_ok(Q[1], n[2], k[2]);
+    T* A1 = tail ? ar.take<T>(Q[1] * n[2]) : nullptr;
     for (int j = 0; j < d; ++j) {
         const int dj = d - j;
         const T* src = j == 0 ? A : R[j];
@@ -207,16 +216,24 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
         const T* Gw;
         const bool p2 = j == 0 && fused &&
                         plane2_eligible(n[d - 2], n[d - 1], k[d - 2], k[d - 1], (int)sizeof(T));
-        if (p2 && Q[0] <= 32) {
+        if (j == 0 && scan0) {
             // middle axes by the generic passes; the two trailing axes and the
             // block scans in one pass (the box-summed planes are not stored)
             const T* G1 = filter_axes<T>(Ga, gn, gk, dj, 1, dj - 3, gb0, gb1, dry, sink);
             // the streaming kernel reads the block prefix only where its runs start
             if (!dry)
-                sink.plane_scan(G1, Ga, PX[0], SX[0], R[1], Q[0], prod(n, 1, d - 2), n[d - 2],
-                                n[d - 1], k[d - 2], k[d - 1],
+                sink.plane_scan(G1, Ga, PX[0], SX[0], R[1], A1, Q[0], prod(n, 1, d - 2),
+                                n[d - 2], n[d - 1], k[d - 2], k[d - 1],
                                 plane_axis0_run_blocks(Q[0], prod(n, 1, d - 2), n[d - 2],
                                                        n[d - 1], k[d - 2], k[d - 1]));
+            if (tail) {
+                // levels 1 and 2; Exc_2 goes where the bottom-up pass expects it
+                sink.level(1);
+                if (!dry)
+                    sink.tail_scan(A1, PX[1], SX[1], tb[(d - 1) % 2], Q[1], n[2], k[2],
+                                   row_axis0_run_blocks(Q[1], n[2], k[2]));
+                break;
+            }
             continue;
         }
         if (p2) {
@@ -240,6 +257,7 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
         sink.level(j);
         T* out = j == 0 ? exc : tb[j % 2];
         const T* Trest = j == d - 1 ? nullptr : tb[(j + 1) % 2];
+        if (j == d - 1 && tail) continue;
         if (j == d - 1 && last_small) {
             if (!dry) sink.ex1d_small(src, out, n[j], k[j]);
             continue;

@@ -572,6 +572,7 @@ struct PlaneScanArgs {
     void* PX;
     void* SX;
     void* R;         // (M) or null
+    void* A1;        // (ceil(NY / ky), NX): op of R over each ky-row block, or null (MID == 1)
     i64 Q, MID, NY, NX, M;
     int ky, kx;
     int pxe;         // PX is stored for blocks q with q % pxe == 0 only
@@ -714,6 +715,22 @@ __global__ void __launch_bounds__(1024) k_plane_scan(PlaneScanArgs a) {
             for (int u = 0; u < P; ++u) gw[q0 + P + u] = q0 + P + u < Q ? sW[u * NT + tid] : e;
         }
     }
+    if (a.A1) {
+        // the next level's block aggregates: R (the reduction over axis 0)
+        // reduced over each ky-row block of the tile; the tile holds whole
+        // blocks, and invalid slots hold the identity
+        __syncthreads();
+        sW[tid] = pvalid ? Rm : e;
+        __syncthreads();
+        if (tid < C::NBY * C::TXM) {
+            const int b = tid / C::TXM, c = tid % C::TXM;
+            const int cx = (c / KP) * kx + c % KP;
+            T g = e;
+            for (int r = 0; r < ky; ++r) g = Op::apply(g, sW[(b * KP + r) * C::TXM + c]);
+            if (c % KP < kx && x0 + cx < NX && y0 + b * ky < NY)
+                ((T*)a.A1)[(i64)(y0 / ky + b) * NX + x0 + cx] = g;
+        }
+    }
     if (!pvalid) return;
     const i64 m = (i64)mid * plane + (i64)(y0 + py) * NX + x0 + px;
     T* __restrict__ PX = (T*)a.PX;
@@ -749,11 +766,11 @@ void launch_plane_scan_kp(PlaneScanArgs pa, hipStream_t st) {
 }
 
 template <typename T, class Op>
-void launch_plane_scan(const T* G, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 MID, i64 NY,
-                       i64 NX, i64 ky, i64 kx, i64 pxe, hipStream_t st) {
+void launch_plane_scan(const T* G, const T* Ga, T* PX, T* SX, T* R, T* A1, i64 Q, i64 MID,
+                       i64 NY, i64 NX, i64 ky, i64 kx, i64 pxe, hipStream_t st) {
     KTimer timer("k_plane_scan", st);
     PlaneScanArgs pa{};
-    pa.G = G; pa.Ga = Ga; pa.PX = PX; pa.SX = SX; pa.R = R;
+    pa.G = G; pa.Ga = Ga; pa.PX = PX; pa.SX = SX; pa.R = R; pa.A1 = MID == 1 ? A1 : nullptr;
     pa.Q = Q; pa.MID = MID; pa.NY = NY; pa.NX = NX; pa.M = MID * NY * NX;
     pa.ky = (int)ky; pa.kx = (int)kx; pa.pxe = (int)pxe;
     const i64 km = ky > kx ? ky : kx;

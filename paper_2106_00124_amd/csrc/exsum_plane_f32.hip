@@ -43,9 +43,9 @@ template void launch_plane_bdbs<float, OpSum>(const float*, float*, i64, i64, i6
                                              hipStream_t);
 template void launch_plane_bdbs<float, OpMax>(const float*, float*, i64, i64, i64, i64, i64,
                                              hipStream_t);
-template void launch_plane_scan<float, OpSum>(const float*, const float*, float*, float*, float*, i64, i64,
+template void launch_plane_scan<float, OpSum>(const float*, const float*, float*, float*, float*, float*, i64, i64,
                                             i64, i64, i64, i64, i64, hipStream_t);
-template void launch_plane_scan<float, OpMax>(const float*, const float*, float*, float*, float*, i64, i64,
+template void launch_plane_scan<float, OpMax>(const float*, const float*, float*, float*, float*, float*, i64, i64,
                                             i64, i64, i64, i64, i64, hipStream_t);
 template void launch_plane_weak<float, OpSum>(const float*, float*, const float*, float*, i64, i64,
                                               i64, i64, i64, i64, i64, hipStream_t);

@@ -12,9 +12,9 @@ template void launch_plane_bdbs<int, OpSum>(const int*, int*, i64, i64, i64, i64
                                              hipStream_t);
 template void launch_plane_bdbs<int, OpMax>(const int*, int*, i64, i64, i64, i64, i64,
                                              hipStream_t);
-template void launch_plane_scan<int, OpSum>(const int*, const int*, int*, int*, int*, i64, i64,
+template void launch_plane_scan<int, OpSum>(const int*, const int*, int*, int*, int*, int*, i64, i64,
                                             i64, i64, i64, i64, i64, hipStream_t);
-template void launch_plane_scan<int, OpMax>(const int*, const int*, int*, int*, int*, i64, i64,
+template void launch_plane_scan<int, OpMax>(const int*, const int*, int*, int*, int*, int*, i64, i64,
                                             i64, i64, i64, i64, i64, hipStream_t);
 template void launch_plane_weak<int, OpSum>(const int*, int*, const int*, int*, i64, i64, i64, i64,
                                             i64, i64, i64, hipStream_t);

@@ -13,6 +13,8 @@ bool row_eligible(i64 n0, i64 NX, i64 k0, i64 kx, int es) {
     return (double)NX / ((double)row_tiles(NX, kx) * 256.0) >= 0.25;
 }
 
+i64 row_axis0_run_blocks(i64 Q, i64 NX, i64 kx) { return row_run_blocks(Q, NX, kx); }
+
 template void launch_row_axis0<float, OpSum>(const float*, const float*, const float*, const float*,
                                              float*, float*, i64, i64, i64, i64, i64, hipStream_t);
 template void launch_row_axis0<float, OpMax>(const float*, const float*, const float*, const float*,

@@ -77,8 +77,16 @@ PLANE_CASES = [
     ((33, 64, 31), (16, 5, 3)),
     ((65, 47, 48), (13, 16, 9)),
     # 32 blocks along axis 0 (one-pass block scans) and 33 (separate passes)
-    ((64, 40, 36), (2, 5, 3)),
-    ((66, 40, 36), (2, 5, 3)),
+    ((64, 40, 40), (2, 5, 5)),
+    ((66, 40, 40), (2, 5, 5)),
+    # levels 1 and 2 from the level-0 scan's block aggregates in one
+    # workgroup: the largest table it takes (32 blocks x 512) and one block
+    # more (the separate passes), the longest last level it takes (4096) and
+    # a table too big with a long last level
+    ((6, 128, 512), (3, 4, 8)),
+    ((6, 132, 512), (3, 4, 8)),
+    ((4, 32, 4096), (2, 16, 16)),
+    ((4, 160, 2048), (2, 16, 16)),
     # 64 tiles: four runs of eight blocks along axis 0
     ((64, 256, 256), (2, 16, 16)),
 ]
