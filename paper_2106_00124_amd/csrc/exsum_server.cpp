@@ -232,7 +232,9 @@ static void worker_loop(exs_server* s) {
         lk.unlock();
         std::vector<std::pair<Request*, exs_status>> res;
         for (Request* r : go) res.emplace_back(r, launch(s, *r));
-        if (go.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        // while work is in flight the worker polls the slot events: a timed
+        // sleep would add the kernel timer's slack to every request's latency
+        if (go.empty()) std::this_thread::yield();
         lk.lock();
         for (auto& pr : res) {
             Request& r = *pr.first;
