@@ -154,6 +154,10 @@ struct EagerSink {
         launch_blockagg<T, Op>(X, Ga, n0, M, k0, Q, st);
     }
     bool small1d_ok(i64 n) const { return ex1d_small_ok(n); }
+    bool long1d_ok(i64 n, i64 k) const { return sizeof(T) == 4 && exs::long1d_ok(n, k); }
+    void long1d(const T* A, T* exc, T* inc, i64 n, i64 k, T* Tt, T* Ut, T* CP, T* CS) {
+        if constexpr (sizeof(T) == 4) launch_long1d<T, Op>(A, exc, inc, n, k, Tt, Ut, CP, CS, st);
+    }
     bool tail_ok(i64 Q, i64 n, i64 k) const { return sizeof(T) == 4 && tail_scan_ok(Q, n, k); }
     void tail_scan(const T* A1, T* PX, T* SX, T* exc2, i64 Q, i64 n, i64 k, i64 pxe) {
         if constexpr (sizeof(T) == 4) launch_tail_scan<T, Op>(A1, PX, SX, exc2, Q, n, k, pxe, st);

@@ -59,6 +59,8 @@ struct ListSink {
     void row_axis0(const T*, const T*, const T*, const T*, T*, T*, i64, i64, i64, i64, i64) {}
     // the single-workgroup kernel for a short last level has no work-list form
     bool small1d_ok(i64) const { return false; }
+    bool long1d_ok(i64, i64) const { return false; }
+    void long1d(const T*, T*, T*, i64, i64, T*, T*, T*, T*) {}
     void ex1d_small(const T*, T*, i64, i64) {}
     // weak excluded sums are rejected when the batch is created
     void total(const T*, i64, void*, T*) {}

@@ -89,6 +89,27 @@ __device__ __forceinline__ i64 gtid() {
 // compile-time bound on the block length so the arrays live in VGPRs.
 // Blocks [b0, b1) of the row are produced.
 // ---------------------------------------------------------------------------
+// Scans of the 64 lanes of a wavefront: inclusive prefix (toward higher
+// lanes) and inclusive suffix (toward lower lanes) of one value per lane.
+template <typename T, class Op>
+__device__ __forceinline__ T wave_prefix(T v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T o = __shfl_up(v, off, 64);
+        if (lane >= off) v = Op::apply(o, v);
+    }
+    return v;
+}
+template <typename T, class Op>
+__device__ __forceinline__ T wave_suffix(T v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T o = __shfl_down(v, off, 64);
+        if (lane + off < 64) v = Op::apply(v, o);
+    }
+    return v;
+}
+
 template <typename T, class Op, int KB>
 __device__ __forceinline__ void bdbs_row(const T* __restrict__ src, T* __restrict__ dst,
                                          i64 n, i64 stride, int k, i64 b0, i64 b1) {

@@ -1,0 +1,279 @@
+// exsum_ex1d.hip -- excluded (and included) sums of a long 1-D level, for
+// 4-byte element types and boxes of at most 16.
+//
+// Paper: Xu, Fraser, Leiserson, "Multidimensional Included and Excluded Sums"
+// (SIAM ACDA 2021, arXiv 2106.00124).
+//
+// At the last dimension-reduction level (Sec. 5) only the prefix before x and
+// the suffix from x + k remain: Exc[x] = P[x - 1] op S[x + k], with P and S the
+// inclusive prefix and suffix along the axis.  The axis is cut into chunks of C
+// elements (C a multiple of k); three launches:
+//   k_l1_tot   per chunk: its total T[c] and U[c], the total without its first
+//              k elements;
+//   k_l1_scan  one workgroup: the exclusive prefix CP and suffix CS of T;
+//   k_l1_out   per chunk, staged in LDS with the first k elements of the next
+//              chunk: the workgroup's prefix and suffix scans plus CP[c] and
+//              CS[c] give P and S on the chunk; S past the chunk is the next
+//              chunk's first k elements op U[c + 1] op CS[c + 1].  The included
+//              sum is BDBS (Sec. 3): each thread owns whole k-blocks, so the
+//              block's range suffix is a thread-local scan and the next
+//              block's range prefix is read from LDS.
+#include "exsum_internal.hpp"
+#include "exsum_device.hpp"
+
+namespace exs {
+
+constexpr int L1_THREADS = 256;
+constexpr int L1_MAXE = 30;                      // k * ceil(16 / k) for k <= 16
+constexpr int L1_SCAN_THREADS = 1024, L1_SCAN_PER = 8;
+constexpr int L1_MAX_CHUNKS = L1_SCAN_THREADS * L1_SCAN_PER;
+
+// elements per thread: whole k-blocks, at least 16
+static inline int l1_elems(i64 k) { return (int)(k * ((16 + k - 1) / k)); }
+
+// LDS slot of chunk element i: one pad word per 32 spreads the per-thread
+// runs over the banks
+__host__ __device__ constexpr int l1p(int i) { return i + (i >> 5); }
+
+template <typename T, class Op>
+__device__ __forceinline__ T l1_wg_reduce(T v, T* red) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = Op::apply(v, __shfl_xor(v, off, 64));
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    T r = red[0];
+#pragma unroll
+    for (int w = 1; w < L1_THREADS / 64; ++w) r = Op::apply(r, red[w]);
+    return r;
+}
+
+template <typename T, class Op>
+__global__ __launch_bounds__(L1_THREADS) void k_l1_tot(const T* __restrict__ A,
+                                                       T* __restrict__ Tt, T* __restrict__ Ut,
+                                                       i64 n, int C, int k) {
+    __shared__ T red[2][L1_THREADS / 64];
+    const T e = Op::template id<T>();
+    const i64 base = (i64)blockIdx.x * C;
+    const int len = n - base < C ? (int)(n - base) : C;
+    T s = e, u = e;
+#pragma unroll 8
+    for (int i = threadIdx.x; i < len; i += L1_THREADS) {
+        const T v = A[base + i];
+        s = Op::apply(s, v);
+        if (i >= k) u = Op::apply(u, v);
+    }
+    s = l1_wg_reduce<T, Op>(s, red[0]);
+    u = l1_wg_reduce<T, Op>(u, red[1]);
+    if (threadIdx.x == 0) {
+        Tt[blockIdx.x] = s;
+        Ut[blockIdx.x] = u;
+    }
+}
+
+template <typename T, class Op>
+__global__ __launch_bounds__(L1_SCAN_THREADS) void k_l1_scan(const T* __restrict__ Tt,
+                                                             T* __restrict__ CP,
+                                                             T* __restrict__ CS, int nc) {
+    __shared__ T wt[2][L1_SCAN_THREADS / 64];
+    const T e = Op::template id<T>();
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int b0 = t * L1_SCAN_PER;
+    T v[L1_SCAN_PER];
+#pragma unroll
+    for (int r = 0; r < L1_SCAN_PER; ++r) v[r] = b0 + r < nc ? Tt[b0 + r] : e;
+    T run = e;
+#pragma unroll
+    for (int r = 0; r < L1_SCAN_PER; ++r) run = Op::apply(run, v[r]);
+    const T ip = wave_prefix<T, Op>(run, lane);
+    const T is = wave_suffix<T, Op>(run, lane);
+    if (lane == 63) wt[0][wv] = ip;
+    if (lane == 0) wt[1][wv] = is;
+    __syncthreads();
+    T lo = e, hi = e;
+    for (int w = 0; w < wv; ++w) lo = Op::apply(lo, wt[0][w]);
+    for (int w = L1_SCAN_THREADS / 64 - 1; w > wv; --w) hi = Op::apply(wt[1][w], hi);
+    const T up = __shfl_up(ip, 1, 64), dn = __shfl_down(is, 1, 64);
+    T before = lane > 0 ? Op::apply(lo, up) : lo;
+    T after = lane < 63 ? Op::apply(dn, hi) : hi;
+#pragma unroll
+    for (int r = 0; r < L1_SCAN_PER; ++r) {
+        if (b0 + r < nc) CP[b0 + r] = before;
+        before = Op::apply(before, v[r]);
+    }
+#pragma unroll
+    for (int r = L1_SCAN_PER - 1; r >= 0; --r) {
+        if (b0 + r < nc) CS[b0 + r] = after;
+        after = Op::apply(v[r], after);
+    }
+}
+
+template <typename T, class Op>
+__global__ __launch_bounds__(L1_THREADS) void k_l1_out(const T* __restrict__ A,
+                                                       const T* __restrict__ CP,
+                                                       const T* __restrict__ CS,
+                                                       const T* __restrict__ Ut,
+                                                       T* __restrict__ exc, T* __restrict__ inc,
+                                                       i64 n, int C, int E, int k) {
+    // LDS sized for this chunk length (launch_long1d): the staged chunk with
+    // its halo, then the suffixes
+    extern __shared__ __align__(16) unsigned char l1_lds[];
+    T* raw = (T*)l1_lds;
+    T* suf = raw + l1p(C + k) + 1;
+    __shared__ T wt[2][L1_THREADS / 64];
+    __shared__ T hs[16];
+    const T e = Op::template id<T>();
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const i64 c = blockIdx.x, base = c * C;
+    const int len = n - base < C ? (int)(n - base) : C;
+    const i64 after_chunk = n - (base + C);
+    const int hlen = after_chunk <= 0 ? 0 : (after_chunk < k ? (int)after_chunk : k);
+
+    // the chunk's offsets, issued with the chunk loads
+    const T cp = CP[c], cs = CS[c];
+    const T tail = hlen > 0 ? Op::apply(Ut[c + 1], CS[c + 1]) : e;
+    // the chunk and the first k elements of the next one, identity past them
+    // (all loads issued before the first LDS write)
+    {
+        T g[L1_MAXE + 1];
+#pragma unroll
+        for (int r = 0; r <= L1_MAXE; ++r) {
+            const int i = t + r * L1_THREADS;
+            g[r] = i < len + hlen ? A[base + i] : e;
+        }
+#pragma unroll
+        for (int r = 0; r <= L1_MAXE; ++r) {
+            const int i = t + r * L1_THREADS;
+            if (i < C + k) raw[l1p(i)] = g[r];
+        }
+    }
+    __syncthreads();
+
+    // this thread's run of E elements (whole k-blocks)
+    const int x0 = t * E;
+    T v[L1_MAXE];
+#pragma unroll
+    for (int r = 0; r < L1_MAXE; ++r) v[r] = r < E ? raw[l1p(x0 + r)] : e;
+    T run = e;
+#pragma unroll
+    for (int r = 0; r < L1_MAXE; ++r) run = Op::apply(run, v[r]);
+    const T ip = wave_prefix<T, Op>(run, lane);
+    const T is = wave_suffix<T, Op>(run, lane);
+    if (lane == 63) wt[0][wv] = ip;
+    if (lane == 0) wt[1][wv] = is;
+    if (t == 0 && hlen > 0) {
+        // inclusive suffixes inside the next chunk's first k elements
+        T s = tail;
+        for (int r = k - 1; r >= 0; --r) {
+            s = Op::apply(raw[l1p(C + r)], s);
+            hs[r] = s;
+        }
+    }
+    __syncthreads();
+    T lo = cp, hi = cs;
+    for (int w = 0; w < wv; ++w) lo = Op::apply(lo, wt[0][w]);
+    for (int w = L1_THREADS / 64 - 1; w > wv; --w) hi = Op::apply(wt[1][w], hi);
+    const T up = __shfl_up(ip, 1, 64), dn = __shfl_down(is, 1, 64);
+    const T pre = lane > 0 ? Op::apply(lo, up) : lo;   // P before x0
+    T s = lane < 63 ? Op::apply(dn, hi) : hi;          // S after the run
+    // inclusive suffixes S[x0 + r] for the other threads, and the range
+    // suffixes of this thread's k-blocks (the first half of BDBS)
+    T bs[L1_MAXE];
+    T b = e;
+    int left = 0;  // elements of the current block still below r
+#pragma unroll
+    for (int r = L1_MAXE - 1; r >= 0; --r) {
+        if (r < E) {
+            s = Op::apply(v[r], s);
+            suf[l1p(x0 + r)] = s;
+            b = left == 0 ? v[r] : Op::apply(v[r], b);
+            left = left == 0 ? k - 1 : left - 1;
+        }
+        bs[r] = b;
+    }
+    __syncthreads();
+    // Exc[x] = P[x - 1] op S[x + k]; Inc[x] = range suffix op range prefix of
+    // the next block up to x + k - 1 (the next block may be the next thread's
+    // or past the chunk: it is read from LDS)
+    T ex[L1_MAXE];
+    T p = pre, q = e;
+    int o = 0;  // offset of x0 + r in its block
+#pragma unroll
+    for (int r = 0; r < L1_MAXE; ++r) {
+        if (r < E) {
+            const int y = x0 + r + k;
+            T sy;
+            if (base + y >= n) sy = e;
+            else if (y < C) sy = suf[l1p(y)];
+            else sy = hs[y - C];
+            ex[r] = Op::apply(p, sy);
+            p = Op::apply(p, v[r]);
+            q = o == 0 ? e : Op::apply(q, raw[l1p(x0 + r + k - 1)]);
+            bs[r] = o == 0 ? bs[r] : Op::apply(bs[r], q);
+            o = o + 1 == k ? 0 : o + 1;
+        }
+    }
+    // coalesced stores through LDS
+    __syncthreads();
+    if (exc) {
+#pragma unroll
+        for (int r = 0; r < L1_MAXE; ++r)
+            if (r < E) raw[l1p(x0 + r)] = ex[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < L1_MAXE; ++r) {
+            const int i = t + r * L1_THREADS;
+            if (i < len) exc[base + i] = raw[l1p(i)];
+        }
+        __syncthreads();
+    }
+    if (inc) {
+#pragma unroll
+        for (int r = 0; r < L1_MAXE; ++r)
+            if (r < E) raw[l1p(x0 + r)] = bs[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < L1_MAXE; ++r) {
+            const int i = t + r * L1_THREADS;
+            if (i < len) inc[base + i] = raw[l1p(i)];
+        }
+    }
+}
+
+i64 long1d_chunks(i64 n, i64 k) { return (n + (i64)L1_THREADS * l1_elems(k) - 1) / ((i64)L1_THREADS * l1_elems(k)); }
+
+bool long1d_ok(i64 n, i64 k) {
+    return k <= 16 && n < ((i64)1 << 31) - 64 && long1d_chunks(n, k) <= L1_MAX_CHUNKS;
+}
+
+template <typename T, class Op>
+void launch_long1d(const T* A, T* exc, T* inc, i64 n, i64 k, T* Tt, T* Ut, T* CP, T* CS,
+                   hipStream_t st) {
+    const int E = l1_elems(k), C = L1_THREADS * E;
+    const i64 nc = long1d_chunks(n, k);
+    {
+        KTimer timer("k_l1_tot", st);
+        hipLaunchKernelGGL((k_l1_tot<T, Op>), dim3((unsigned)nc), dim3(L1_THREADS), 0, st, A, Tt,
+                           Ut, n, C, (int)k);
+    }
+    {
+        KTimer timer("k_l1_scan", st);
+        hipLaunchKernelGGL((k_l1_scan<T, Op>), dim3(1), dim3(L1_SCAN_THREADS), 0, st, Tt, CP, CS,
+                           (int)nc);
+    }
+    KTimer timer("k_l1_out", st);
+    const size_t lds = ((size_t)l1p(C + (int)k) + 1 + (size_t)l1p(C) + 1) * sizeof(T);
+    hipLaunchKernelGGL((k_l1_out<T, Op>), dim3((unsigned)nc), dim3(L1_THREADS), lds, st, A, CP,
+                       CS, Ut, exc, inc, n, C, E, (int)k);
+}
+
+template void launch_long1d<float, OpSum>(const float*, float*, float*, i64, i64, float*, float*,
+                                          float*, float*, hipStream_t);
+template void launch_long1d<float, OpMax>(const float*, float*, float*, i64, i64, float*, float*,
+                                          float*, float*, hipStream_t);
+template void launch_long1d<int, OpSum>(const int*, int*, int*, i64, i64, int*, int*, int*, int*,
+                                        hipStream_t);
+template void launch_long1d<int, OpMax>(const int*, int*, int*, i64, i64, int*, int*, int*, int*,
+                                        hipStream_t);
+
+}  // namespace exs

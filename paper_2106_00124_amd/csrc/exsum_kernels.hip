@@ -103,27 +103,6 @@ __global__ __launch_bounds__(1024) void k_ex1d_small(const T* __restrict__ R, T*
     }
 }
 
-// Scans of 64 lanes: inclusive prefix (toward higher lanes) and inclusive
-// suffix (toward lower lanes) of one value per lane.
-template <typename T, class Op>
-__device__ __forceinline__ T wave_prefix(T v, int lane) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const T o = __shfl_up(v, off, 64);
-        if (lane >= off) v = Op::apply(o, v);
-    }
-    return v;
-}
-template <typename T, class Op>
-__device__ __forceinline__ T wave_suffix(T v, int lane) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const T o = __shfl_down(v, off, 64);
-        if (lane + off < 64) v = Op::apply(v, o);
-    }
-    return v;
-}
-
 // The last two levels of a rank-3 tensor in one workgroup, from the level-1
 // block aggregates A1 (Q blocks of k0 rows of R_1, n columns; written by the
 // level-0 scan kernel, so R_1 itself is not read here):

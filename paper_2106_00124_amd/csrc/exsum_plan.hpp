@@ -194,6 +194,16 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
     // the last level is 1-D; when short, one workgroup computes its excluded
     // sums directly from R_{d-1} (no block passes)
     const bool last_small = d >= 2 && sink.small1d_ok(n[d - 1]);
+    // when long, in chunks: chunk totals, their scans, one pass over the axis
+    const bool last_long = !last_small && sink.long1d_ok(n[d - 1], k[d - 1]);
+    T *c_tot = nullptr, *c_rest = nullptr, *c_pre = nullptr, *c_suf = nullptr;
+    if (last_long) {
+        const i64 nc = long1d_chunks(n[d - 1], k[d - 1]);
+        c_tot = ar.take<T>(nc);
+        c_rest = ar.take<T>(nc);
+        c_pre = ar.take<T>(nc);
+        c_suf = ar.take<T>(nc);
+    }
     // rank 3 with the one-pass level-0 scan: that pass also reduces R_1 over
     // the level-1 blocks (its tiles hold whole blocks), and when that table
     // is small one workgroup finishes levels 1 and 2 from it (box-sums, block
@@ -206,7 +216,7 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
     for (int j = 0; j < d; ++j) {
         const int dj = d - j;
         const T* src = j == 0 ? A : R[j];
-        if (j == d - 1 && last_small) break;
+        if (j == d - 1 && (last_small || last_long)) break;
         sink.level(j);
         if (!dry) sink.blockagg(src, Ga, n[j], M[j], k[j], Q[j]);
         i64 gn[EXS_MAX_RANK], gk[EXS_MAX_RANK];
@@ -260,6 +270,12 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
         if (j == d - 1 && tail) continue;
         if (j == d - 1 && last_small) {
             if (!dry) sink.ex1d_small(src, out, n[j], k[j]);
+            continue;
+        }
+        if (j == d - 1 && last_long) {
+            if (!dry)
+                sink.long1d(src, out, j == 0 ? inc : nullptr, n[j], k[j], c_tot, c_rest, c_pre,
+                            c_suf);
             continue;
         }
         if (j == 0 && fused) {

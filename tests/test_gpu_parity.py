@@ -34,9 +34,19 @@ CASES = [
     # many blocks along an axis with few points (segmented block scans)
     ((300000,), (3,)),
     ((50000, 3), (2, 2)),
-    # a last level longer than the one-workgroup kernel takes
+    # a last level longer than the one-workgroup kernel takes (4-byte types
+    # with k <= 16: in chunks with a one-workgroup scan of the chunk totals;
+    # k = 16 and k = 15 give the shortest and longest chunks, k = 1 a chunk
+    # per 4096 elements, ragged chunks and blocks throughout)
     ((3, 9000), (2, 5)),
     ((2, 3, 8193), (1, 2, 100)),
+    ((100003,), (7,)),
+    ((50000,), (16,)),
+    ((61441,), (15,)),
+    ((20000,), (1,)),
+    ((5,), (5,)),
+    ((2, 40000), (2, 16)),
+    ((3, 3, 20000), (2, 2, 11)),
     # enough rows along the contiguous axis for the LDS-staged row kernel
     ((65536, 130), (3, 5)),
     ((256, 64, 200), (2, 3, 64)),
