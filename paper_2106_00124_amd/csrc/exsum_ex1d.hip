@@ -19,7 +19,7 @@
 //              block's range suffix is a thread-local scan and the next
 //              block's range prefix is read from LDS.
 #include "exsum_internal.hpp"
-#include "exsum_device.hpp"
+#include "exsum_plane.hpp"
 
 namespace exs {
 
@@ -30,10 +30,6 @@ constexpr int L1_MAX_CHUNKS = L1_SCAN_THREADS * L1_SCAN_PER;
 
 // elements per thread: whole k-blocks, at least 16
 static inline int l1_elems(i64 k) { return (int)(k * ((16 + k - 1) / k)); }
-
-// LDS slot of chunk element i: one pad word per 32 spreads the per-thread
-// runs over the banks
-__host__ __device__ constexpr int l1p(int i) { return i + (i >> 5); }
 
 template <typename T, class Op>
 __device__ __forceinline__ T l1_wg_reduce(T v, T* red) {
@@ -108,55 +104,64 @@ __global__ __launch_bounds__(L1_SCAN_THREADS) void k_l1_scan(const T* __restrict
     }
 }
 
-template <typename T, class Op>
+// E (elements per thread) is a template parameter so that every loop has a
+// fixed trip count.  In LDS each thread's run of E elements sits at
+// t * (E + 1) (one pad word per run: distinct banks for the lanes, and every
+// access of a run is the thread's base plus a constant); the first k elements
+// of the next chunk are run L1_THREADS.
+template <typename T, class Op, int E>
 __global__ __launch_bounds__(L1_THREADS) void k_l1_out(const T* __restrict__ A,
                                                        const T* __restrict__ CP,
                                                        const T* __restrict__ CS,
                                                        const T* __restrict__ Ut,
                                                        T* __restrict__ exc, T* __restrict__ inc,
-                                                       i64 n, int C, int E, int k) {
-    // LDS sized for this chunk length (launch_long1d): the staged chunk with
-    // its halo, then the suffixes
-    extern __shared__ __align__(16) unsigned char l1_lds[];
-    T* raw = (T*)l1_lds;
-    T* suf = raw + l1p(C + k) + 1;
+                                                       i64 n, int k) {
+    constexpr int C = L1_THREADS * E, RS = E + 1;
+    constexpr int NR = (C + 16 + L1_THREADS - 1) / L1_THREADS;  // staging rounds, halo included
+    __shared__ T raw[(L1_THREADS + 1) * RS];
+    __shared__ T suf[L1_THREADS * RS];
     __shared__ T wt[2][L1_THREADS / 64];
     __shared__ T hs[16];
     const T e = Op::template id<T>();
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const i64 c = blockIdx.x, base = c * C;
-    const int len = n - base < C ? (int)(n - base) : C;
-    const i64 after_chunk = n - (base + C);
-    const int hlen = after_chunk <= 0 ? 0 : (after_chunk < k ? (int)after_chunk : k);
+    // elements from the chunk start to the end of the tensor (capped)
+    const int rem = n - base < C + 16 ? (int)(n - base) : C + 16;
+    const int len = rem < C ? rem : C;
+    const int hlen = rem - C <= 0 ? 0 : (rem - C < k ? rem - C : k);
+    const int lim = len + hlen;
 
-    // the chunk's offsets, issued with the chunk loads
-    const T cp = CP[c], cs = CS[c];
-    const T tail = hlen > 0 ? Op::apply(Ut[c + 1], CS[c + 1]) : e;
-    // the chunk and the first k elements of the next one, identity past them
-    // (all loads issued before the first LDS write)
+    // the chunk's offsets (excluded sums only), issued with the chunk loads
+    const T cp = exc ? CP[c] : e, cs = exc ? CS[c] : e;
+    const T tail = exc && hlen > 0 ? Op::apply(Ut[c + 1], CS[c + 1]) : e;
+    // the chunk and the first k elements of the next one (identity past them):
+    // coalesced loads, all issued before the first LDS write
     {
-        T g[L1_MAXE + 1];
+        const __amdgpu_buffer_rsrc_t src = buf(A + base, (unsigned)lim * sizeof(T));
+        T g[NR];
 #pragma unroll
-        for (int r = 0; r <= L1_MAXE; ++r) {
+        for (int r = 0; r < NR; ++r) {
             const int i = t + r * L1_THREADS;
-            g[r] = i < len + hlen ? A[base + i] : e;
+            const T x = bload<T>(src, (unsigned)i * sizeof(T));
+            g[r] = i < lim ? x : e;
         }
 #pragma unroll
-        for (int r = 0; r <= L1_MAXE; ++r) {
+        for (int r = 0; r < NR; ++r) {
             const int i = t + r * L1_THREADS;
-            if (i < C + k) raw[l1p(i)] = g[r];
+            if (i < C + 16) raw[(i / E) * RS + i % E] = g[r];
         }
     }
     __syncthreads();
 
-    // this thread's run of E elements (whole k-blocks)
     const int x0 = t * E;
-    T v[L1_MAXE];
+    T* const my_raw = raw + t * RS;
+    T* const my_suf = suf + t * RS;
+    T v[E];
 #pragma unroll
-    for (int r = 0; r < L1_MAXE; ++r) v[r] = r < E ? raw[l1p(x0 + r)] : e;
+    for (int r = 0; r < E; ++r) v[r] = my_raw[r];
     T run = e;
 #pragma unroll
-    for (int r = 0; r < L1_MAXE; ++r) run = Op::apply(run, v[r]);
+    for (int r = 0; r < E; ++r) run = Op::apply(run, v[r]);
     const T ip = wave_prefix<T, Op>(run, lane);
     const T is = wave_suffix<T, Op>(run, lane);
     if (lane == 63) wt[0][wv] = ip;
@@ -165,77 +170,79 @@ __global__ __launch_bounds__(L1_THREADS) void k_l1_out(const T* __restrict__ A,
         // inclusive suffixes inside the next chunk's first k elements
         T s = tail;
         for (int r = k - 1; r >= 0; --r) {
-            s = Op::apply(raw[l1p(C + r)], s);
+            s = Op::apply(raw[L1_THREADS * RS + r], s);
             hs[r] = s;
         }
     }
     __syncthreads();
     T lo = cp, hi = cs;
-    for (int w = 0; w < wv; ++w) lo = Op::apply(lo, wt[0][w]);
-    for (int w = L1_THREADS / 64 - 1; w > wv; --w) hi = Op::apply(wt[1][w], hi);
+#pragma unroll
+    for (int w = 0; w < L1_THREADS / 64; ++w)
+        if (w < wv) lo = Op::apply(lo, wt[0][w]);
+#pragma unroll
+    for (int w = L1_THREADS / 64 - 1; w >= 0; --w)
+        if (w > wv) hi = Op::apply(wt[1][w], hi);
     const T up = __shfl_up(ip, 1, 64), dn = __shfl_down(is, 1, 64);
     const T pre = lane > 0 ? Op::apply(lo, up) : lo;   // P before x0
     T s = lane < 63 ? Op::apply(dn, hi) : hi;          // S after the run
     // inclusive suffixes S[x0 + r] for the other threads, and the range
     // suffixes of this thread's k-blocks (the first half of BDBS)
-    T bs[L1_MAXE];
+    T bs[E];
     T b = e;
-    int left = 0;  // elements of the current block still below r
+    int left = 0;  // elements of the current block below r
 #pragma unroll
-    for (int r = L1_MAXE - 1; r >= 0; --r) {
-        if (r < E) {
-            s = Op::apply(v[r], s);
-            suf[l1p(x0 + r)] = s;
-            b = left == 0 ? v[r] : Op::apply(v[r], b);
-            left = left == 0 ? k - 1 : left - 1;
-        }
+    for (int r = E - 1; r >= 0; --r) {
+        s = Op::apply(v[r], s);
+        my_suf[r] = s;
+        b = left == 0 ? v[r] : Op::apply(v[r], b);
+        left = left == 0 ? k - 1 : left - 1;
         bs[r] = b;
     }
     __syncthreads();
-    // Exc[x] = P[x - 1] op S[x + k]; Inc[x] = range suffix op range prefix of
-    // the next block up to x + k - 1 (the next block may be the next thread's
-    // or past the chunk: it is read from LDS)
-    T ex[L1_MAXE];
+    // Exc[x] = P[x - 1] op S[x + k]; Inc[x] = range suffix op the range prefix
+    // of the next block up to x + k - 1.  Position x0 + j (j < 2E) sits at
+    // my_raw[j + (j >= E)]: the next run, or the halo after the last run.
+    T ex[E];
     T p = pre, q = e;
     int o = 0;  // offset of x0 + r in its block
 #pragma unroll
-    for (int r = 0; r < L1_MAXE; ++r) {
-        if (r < E) {
-            const int y = x0 + r + k;
-            T sy;
-            if (base + y >= n) sy = e;
-            else if (y < C) sy = suf[l1p(y)];
-            else sy = hs[y - C];
-            ex[r] = Op::apply(p, sy);
-            p = Op::apply(p, v[r]);
-            q = o == 0 ? e : Op::apply(q, raw[l1p(x0 + r + k - 1)]);
-            bs[r] = o == 0 ? bs[r] : Op::apply(bs[r], q);
-            o = o + 1 == k ? 0 : o + 1;
-        }
+    for (int r = 0; r < E; ++r) {
+        const int j = r + k;
+        T sy;
+        if (x0 + j >= rem) sy = e;
+        else if (t == L1_THREADS - 1 && j >= E) sy = hs[j - E];
+        else sy = my_suf[j + (j >= E ? 1 : 0)];
+        ex[r] = Op::apply(p, sy);
+        p = Op::apply(p, v[r]);
+        const int jp = j - 1;
+        q = o == 0 ? e : Op::apply(q, my_raw[jp + (jp >= E ? 1 : 0)]);
+        bs[r] = o == 0 ? bs[r] : Op::apply(bs[r], q);
+        o = o + 1 == k ? 0 : o + 1;
     }
-    // coalesced stores through LDS
+    // coalesced stores through LDS; the buffer range drops the lanes past the
+    // tensor's end
     __syncthreads();
     if (exc) {
 #pragma unroll
-        for (int r = 0; r < L1_MAXE; ++r)
-            if (r < E) raw[l1p(x0 + r)] = ex[r];
+        for (int r = 0; r < E; ++r) my_raw[r] = ex[r];
         __syncthreads();
+        const __amdgpu_buffer_rsrc_t dst = buf(exc + base, (unsigned)len * sizeof(T));
 #pragma unroll
-        for (int r = 0; r < L1_MAXE; ++r) {
+        for (int r = 0; r < E; ++r) {
             const int i = t + r * L1_THREADS;
-            if (i < len) exc[base + i] = raw[l1p(i)];
+            bstore<T>(dst, (unsigned)i * sizeof(T), raw[(i / E) * RS + i % E]);
         }
         __syncthreads();
     }
     if (inc) {
 #pragma unroll
-        for (int r = 0; r < L1_MAXE; ++r)
-            if (r < E) raw[l1p(x0 + r)] = bs[r];
+        for (int r = 0; r < E; ++r) my_raw[r] = bs[r];
         __syncthreads();
+        const __amdgpu_buffer_rsrc_t dst = buf(inc + base, (unsigned)len * sizeof(T));
 #pragma unroll
-        for (int r = 0; r < L1_MAXE; ++r) {
+        for (int r = 0; r < E; ++r) {
             const int i = t + r * L1_THREADS;
-            if (i < len) inc[base + i] = raw[l1p(i)];
+            bstore<T>(dst, (unsigned)i * sizeof(T), raw[(i / E) * RS + i % E]);
         }
     }
 }
@@ -251,20 +258,36 @@ void launch_long1d(const T* A, T* exc, T* inc, i64 n, i64 k, T* Tt, T* Ut, T* CP
                    hipStream_t st) {
     const int E = l1_elems(k), C = L1_THREADS * E;
     const i64 nc = long1d_chunks(n, k);
-    {
-        KTimer timer("k_l1_tot", st);
-        hipLaunchKernelGGL((k_l1_tot<T, Op>), dim3((unsigned)nc), dim3(L1_THREADS), 0, st, A, Tt,
-                           Ut, n, C, (int)k);
-    }
-    {
+    if (exc) {
+        // the chunk offsets (the included sums alone need none)
+        {
+            KTimer timer("k_l1_tot", st);
+            hipLaunchKernelGGL((k_l1_tot<T, Op>), dim3((unsigned)nc), dim3(L1_THREADS), 0, st, A,
+                               Tt, Ut, n, C, (int)k);
+        }
         KTimer timer("k_l1_scan", st);
         hipLaunchKernelGGL((k_l1_scan<T, Op>), dim3(1), dim3(L1_SCAN_THREADS), 0, st, Tt, CP, CS,
                            (int)nc);
     }
     KTimer timer("k_l1_out", st);
-    const size_t lds = ((size_t)l1p(C + (int)k) + 1 + (size_t)l1p(C) + 1) * sizeof(T);
-    hipLaunchKernelGGL((k_l1_out<T, Op>), dim3((unsigned)nc), dim3(L1_THREADS), lds, st, A, CP,
-                       CS, Ut, exc, inc, n, C, E, (int)k);
+    switch (E) {
+#define EXS_L1_CASE(EE)                                                                          \
+    case EE:                                                                                     \
+        hipLaunchKernelGGL((k_l1_out<T, Op, EE>), dim3((unsigned)nc), dim3(L1_THREADS), 0, st, A, \
+                           CP, CS, Ut, exc, inc, n, (int)k);                                     \
+        break;
+        EXS_L1_CASE(16)
+        EXS_L1_CASE(18)
+        EXS_L1_CASE(20)
+        EXS_L1_CASE(21)
+        EXS_L1_CASE(22)
+        EXS_L1_CASE(24)
+        EXS_L1_CASE(26)
+        EXS_L1_CASE(28)
+        EXS_L1_CASE(30)
+#undef EXS_L1_CASE
+        default: break;
+    }
 }
 
 template void launch_long1d<float, OpSum>(const float*, float*, float*, i64, i64, float*, float*,

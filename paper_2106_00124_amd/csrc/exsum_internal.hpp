@@ -81,9 +81,10 @@ bool plane2_eligible(i64 NY, i64 NX, i64 ky, i64 kx, int es);
 template <typename T, class Op>
 void launch_plane_scan(const T* G, const T* Ga, T* PX, T* SX, T* R, T* A1, i64 Q, i64 MID,
                        i64 NY, i64 NX, i64 ky, i64 kx, i64 pxe, hipStream_t st);
-// excluded (and included) sums of a long 1-D level in chunks (4-byte
+// excluded and/or included sums of a long 1-D level in chunks (4-byte
 // elements, k <= 16): chunk totals, their scans, the chunk pass; the four
-// scratch arrays hold long1d_chunks(n, k) elements each
+// scratch arrays hold long1d_chunks(n, k) elements each (unused, and may be
+// null, when exc is null: the included sums need only the chunk pass)
 bool long1d_ok(i64 n, i64 k);
 i64 long1d_chunks(i64 n, i64 k);
 template <typename T, class Op>

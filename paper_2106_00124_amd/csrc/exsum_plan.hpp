@@ -139,7 +139,10 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
         const T* W = filter_axes<T>(A, n, k, d, 1, d - 1, wb0, wb1, dry, sink);
         T* incb = inc ? inc : exc;
         if (!dry) {
-            sink.bdbs(W, incb, 1, n[0], prod(n, 1, d), k[0]);
+            if (d == 1 && sink.long1d_ok(n[0], k[0]))
+                sink.long1d(A, nullptr, incb, n[0], k[0], nullptr, nullptr, nullptr, nullptr);
+            else
+                sink.bdbs(W, incb, 1, n[0], prod(n, 1, d), k[0]);
             sink.weak_exc(incb, tot, exc, N);
         }
         return EXS_OK;
@@ -158,6 +161,10 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
             if (!dry)
                 sink.row_axis0(A, nullptr, nullptr, nullptr, nullptr, inc, n[0], n[1], k[0], k[1],
                                (n[0] + k[0] - 1) / k[0]);
+            return EXS_OK;
+        }
+        if (d == 1 && sink.long1d_ok(n[0], k[0])) {
+            if (!dry) sink.long1d(A, nullptr, inc, n[0], k[0], nullptr, nullptr, nullptr, nullptr);
             return EXS_OK;
         }
         const T* W = filter_axes<T>(A, n, k, d, 1, d - 1, wb0, wb1, dry, sink);

@@ -116,8 +116,9 @@ def test_parity_plane(orc, shape, box, dtype, op):
 
 
 @pytest.mark.parametrize("mode", ["inc", "exc"])
-def test_single_output_modes(orc, mode):
-    shape, box = (20, 30, 40), (3, 5, 7)
+@pytest.mark.parametrize("shape,box", [((20, 30, 40), (3, 5, 7)), ((50001,), (9,))],
+                         ids=lambda v: "x".join(map(str, v)))
+def test_single_output_modes(orc, mode, shape, box):
     a = make_input(shape, "i32", seed=5, op="sum")
     inc, exc = gpu_run(a, box, "sum", mode)
     assert (inc is None) == (mode == "exc") and (exc is None) == (mode == "inc")
@@ -147,6 +148,7 @@ def test_deterministic(orc):
 
 WEAK_CASES = [
     ((1000,), (64,)),
+    ((50001,), (9,)),
     ((64, 64), (8, 8)),
     ((13, 70), (4, 9)),
     ((33, 17, 65), (16, 16, 16)),
