@@ -107,12 +107,18 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
     // box-sums the two trailing axes itself, the middle axes are done first
     const bool fused = sink.fused_ok && sizeof(T) == 4 && plane_eligible(d, n, k, (int)sizeof(T));
 
+    // included sums (alone, or for the weak excluded sums) of a rank-1 or
+    // rank-2 tensor in one pass: the chunked 1-D kernel or the 2-D stream
+    const bool inc1 = !want_exc && d == 1 && sink.long1d_ok(n[0], k[0]);
+    const bool inc2 = !want_exc && d == 2 && sink.row_ok(n[0], n[1], k[0], k[1]);
     // buffers for box-summed tensors, shared by every level: level j needs
     // (d_j - 1) passes over N_j elements, the fused level 0 only d - 3
     int wb_count = 0;
     i64 wb_elems = 0;
     for (int j = 0; j < (want_exc ? d : 1); ++j) {
-        const int passes = (j == 0 && fused) ? std::max(0, d - 3) : d - j - 1;
+        const int passes = (j == 0 && fused)            ? std::max(0, d - 3)
+                           : (j == 0 && (inc1 || inc2)) ? 0
+                                                        : d - j - 1;
         if (passes > 0) {
             wb_count = std::max(wb_count, std::min(2, passes));
             wb_elems = std::max(wb_elems, prod(n, j, d));
@@ -136,13 +142,21 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
                                 k[0], k[d - 2], k[d - 1]);
             return EXS_OK;
         }
-        const T* W = filter_axes<T>(A, n, k, d, 1, d - 1, wb0, wb1, dry, sink);
         T* incb = inc ? inc : exc;
+        if (inc1 || inc2) {
+            if (!dry) {
+                if (inc1)
+                    sink.long1d(A, nullptr, incb, n[0], k[0], nullptr, nullptr, nullptr, nullptr);
+                else
+                    sink.row_axis0(A, nullptr, nullptr, nullptr, nullptr, incb, n[0], n[1], k[0],
+                                   k[1], (n[0] + k[0] - 1) / k[0]);
+                sink.weak_exc(incb, tot, exc, N);
+            }
+            return EXS_OK;
+        }
+        const T* W = filter_axes<T>(A, n, k, d, 1, d - 1, wb0, wb1, dry, sink);
         if (!dry) {
-            if (d == 1 && sink.long1d_ok(n[0], k[0]))
-                sink.long1d(A, nullptr, incb, n[0], k[0], nullptr, nullptr, nullptr, nullptr);
-            else
-                sink.bdbs(W, incb, 1, n[0], prod(n, 1, d), k[0]);
+            sink.bdbs(W, incb, 1, n[0], prod(n, 1, d), k[0]);
             sink.weak_exc(incb, tot, exc, N);
         }
         return EXS_OK;
@@ -157,13 +171,13 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
                                  (n[0] + k[0] - 1) / k[0]);
             return EXS_OK;
         }
-        if (d == 2 && sink.row_ok(n[0], n[1], k[0], k[1])) {
+        if (inc2) {
             if (!dry)
                 sink.row_axis0(A, nullptr, nullptr, nullptr, nullptr, inc, n[0], n[1], k[0], k[1],
                                (n[0] + k[0] - 1) / k[0]);
             return EXS_OK;
         }
-        if (d == 1 && sink.long1d_ok(n[0], k[0])) {
+        if (inc1) {
             if (!dry) sink.long1d(A, nullptr, inc, n[0], k[0], nullptr, nullptr, nullptr, nullptr);
             return EXS_OK;
         }
