@@ -103,20 +103,25 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
     const bool want_exc = (job->mode & EXS_EXCLUDED) && !weak;  // strong excluded sums
     const bool dry = ar.dry;
     const i64 N = prod(n, 0, d);
-    // level 0 streams axis 0 with the fused plane kernel when it applies; it
-    // box-sums the two trailing axes itself, the middle axes are done first
-    const bool fused = sink.fused_ok && sizeof(T) == 4 && plane_eligible(d, n, k, (int)sizeof(T));
+    // a level of rank >= 3 streams its first axis with the fused plane kernel
+    // when it applies; it box-sums the two trailing axes itself, the middle
+    // axes are done first (levels below 0 only for strong excluded sums)
+    bool fz[EXS_MAX_RANK] = {};
+    for (int j = 0; j < (want_exc ? d : 1); ++j)
+        fz[j] = sink.fused_ok && sizeof(T) == 4 &&
+                plane_eligible(d - j, n + j, k + j, (int)sizeof(T));
+    const bool fused = fz[0];
 
     // included sums (alone, or for the weak excluded sums) of a rank-1 or
     // rank-2 tensor in one pass: the chunked 1-D kernel or the 2-D stream
     const bool inc1 = !want_exc && d == 1 && sink.long1d_ok(n[0], k[0]);
     const bool inc2 = !want_exc && d == 2 && sink.row_ok(n[0], n[1], k[0], k[1]);
     // buffers for box-summed tensors, shared by every level: level j needs
-    // (d_j - 1) passes over N_j elements, the fused level 0 only d - 3
+    // (d_j - 1) passes over N_j elements, a fused level only d_j - 3
     int wb_count = 0;
     i64 wb_elems = 0;
     for (int j = 0; j < (want_exc ? d : 1); ++j) {
-        const int passes = (j == 0 && fused)            ? std::max(0, d - 3)
+        const int passes = fz[j]                        ? std::max(0, d - j - 3)
                            : (j == 0 && (inc1 || inc2)) ? 0
                                                         : d - j - 1;
         if (passes > 0) {
@@ -225,15 +230,21 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
         c_pre = ar.take<T>(nc);
         c_suf = ar.take<T>(nc);
     }
-    // rank 3 with the one-pass level-0 scan: that pass also reduces R_1 over
-    // the level-1 blocks (its tiles hold whole blocks), and when that table
-    // is small one workgroup finishes levels 1 and 2 from it (box-sums, block
-    // scans, the 1-D level); only the level-1 stream then reads R_1
-    const bool scan0 = fused && Q[0] <= 32 &&
-                       plane2_eligible(n[d - 2], n[d - 1], k[d - 2], k[d - 1], (int)sizeof(T));
-    const bool tail = scan0 && d == 3 && sink.row_ok(n[1], n[2], k[1], k[2]) &&
-                      sink.tail_ok(Q[1], n[2], k[2]);
-    T* A1 = tail ? ar.take<T>(Q[1] * n[2]) : nullptr;
+    // fused levels with at most 32 blocks take their block scans in the same
+    // pass as the box-sums of the trailing axes
+    const bool p2ok =
+        d >= 3 && plane2_eligible(n[d - 2], n[d - 1], k[d - 2], k[d - 1], (int)sizeof(T));
+    bool scan[EXS_MAX_RANK] = {};
+    for (int j = 0; j < d; ++j) scan[j] = fz[j] && Q[j] <= 32 && p2ok;
+    // the rank-3 level d - 3, when it takes that pass, also reduces R_{d-2}
+    // over the blocks of level d - 2 (its tiles hold whole blocks); when that
+    // table is small one workgroup finishes the last two levels from it
+    // (box-sums, block scans, the 1-D level), and only the level d - 2
+    // stream then reads R_{d-2}
+    const bool tail = d >= 3 && scan[d - 3] &&
+                      sink.row_ok(n[d - 2], n[d - 1], k[d - 2], k[d - 1]) &&
+                      sink.tail_ok(Q[d - 2], n[d - 1], k[d - 1]);
+    T* A1 = tail ? ar.take<T>(Q[d - 2] * n[d - 1]) : nullptr;
     for (int j = 0; j < d; ++j) {
         const int dj = d - j;
         const T* src = j == 0 ? A : R[j];
@@ -245,36 +256,36 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
         gk[0] = 1;
         for (int a = 1; a < dj; ++a) { gn[a] = n[j + a]; gk[a] = k[j + a]; }
         const T* Gw;
-        const bool p2 = j == 0 && fused &&
-                        plane2_eligible(n[d - 2], n[d - 1], k[d - 2], k[d - 1], (int)sizeof(T));
-        if (j == 0 && scan0) {
+        const i64 mid = prod(n, j + 1, d - 2);
+        if (scan[j]) {
             // middle axes by the generic passes; the two trailing axes and the
             // block scans in one pass (the box-summed planes are not stored)
             const T* G1 = filter_axes<T>(Ga, gn, gk, dj, 1, dj - 3, gb0, gb1, dry, sink);
+            const bool last3 = tail && j == d - 3;
             // the streaming kernel reads the block prefix only where its runs start
             if (!dry)
-                sink.plane_scan(G1, Ga, PX[0], SX[0], R[1], A1, Q[0], prod(n, 1, d - 2),
+                sink.plane_scan(G1, Ga, PX[j], SX[j], R[j + 1], last3 ? A1 : nullptr, Q[j], mid,
                                 n[d - 2], n[d - 1], k[d - 2], k[d - 1],
-                                plane_axis0_run_blocks(Q[0], prod(n, 1, d - 2), n[d - 2],
-                                                       n[d - 1], k[d - 2], k[d - 1]));
-            if (tail) {
-                // levels 1 and 2; Exc_2 goes where the bottom-up pass expects it
-                sink.level(1);
+                                plane_axis0_run_blocks(Q[j], mid, n[d - 2], n[d - 1], k[d - 2],
+                                                       k[d - 1]));
+            if (last3) {
+                // the last two levels; Exc_{d-1} goes where the bottom-up
+                // pass expects it
+                sink.level(d - 2);
                 if (!dry)
-                    sink.tail_scan(A1, PX[1], SX[1], tb[(d - 1) % 2], Q[1], n[2], k[2],
-                                   row_axis0_run_blocks(Q[1], n[2], k[2]));
+                    sink.tail_scan(A1, PX[d - 2], SX[d - 2], tb[(d - 1) % 2], Q[d - 2], n[d - 1],
+                                   k[d - 1], row_axis0_run_blocks(Q[d - 2], n[d - 1], k[d - 1]));
                 break;
             }
             continue;
         }
-        if (p2) {
+        if (fz[j] && p2ok) {
             // middle axes by the generic passes, the two trailing axes in one
             // LDS-tiled pass
             const T* G1 = filter_axes<T>(Ga, gn, gk, dj, 1, dj - 3, gb0, gb1, dry, sink);
             T* G2 = G1 == gb0 ? gb1 : gb0;
             if (!dry)
-                sink.plane_bdbs(G1, G2, Q[0] * prod(n, 1, d - 2), n[d - 2], n[d - 1], k[d - 2],
-                                k[d - 1]);
+                sink.plane_bdbs(G1, G2, Q[j] * mid, n[d - 2], n[d - 1], k[d - 2], k[d - 1]);
             Gw = G2;
         } else {
             Gw = filter_axes<T>(Ga, gn, gk, dj, 1, dj - 1, gb0, gb1, dry, sink);
@@ -299,11 +310,12 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
                             c_suf);
             continue;
         }
-        if (j == 0 && fused) {
-            const T* X0 = filter_axes<T>(A, n, k, d, 1, d - 3, wb0, wb1, dry, sink);
+        if (fz[j]) {
+            const T* X0 = filter_axes<T>(src, n + j, k + j, dj, 1, dj - 3, wb0, wb1, dry, sink);
             if (!dry)
-                sink.plane_axis0(X0, PX[0], SX[0], Trest, exc, inc, n[0], prod(n, 1, d - 2),
-                                 n[d - 2], n[d - 1], k[0], k[d - 2], k[d - 1], Q[0]);
+                sink.plane_axis0(X0, PX[j], SX[j], Trest, out, j == 0 ? inc : nullptr, n[j],
+                                 prod(n, j + 1, d - 2), n[d - 2], n[d - 1], k[j], k[d - 2],
+                                 k[d - 1], Q[j]);
             continue;
         }
         if (dj == 2 && sink.row_ok(n[j], n[j + 1], k[j], k[j + 1])) {
