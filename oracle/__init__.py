@@ -10,19 +10,20 @@ Paper: Xu, Fraser, Leiserson, "Multidimensional Included and Excluded Sums"
 this module only builds it, marshals numpy arrays and widens dtypes:
 
 * floating dtypes ("f32", "f64") are evaluated in float64 (the FP64 reference
-  for f32 inputs; ``max`` is exact);
+  for f32 inputs; ``max`` and ``min`` are exact);
 * integer dtypes ("i32", "i64") are evaluated in int64 with wrapping ``+``; an
   "i32" ``+`` result is reduced modulo 2**32 (returned sign-extended in int64).
 
 Every function takes a row-major numpy array ``a`` of any rank 1..8, a box
-``k`` (sequence of ints, 1 <= k_i <= n_i), ``op`` in {"sum", "max"} and the
+``k`` (sequence of ints, 1 <= k_i <= n_i), ``op`` in {"sum", "max", "min"} and the
 element ``dtype`` the GPU computes in, and returns float64 or int64 arrays.
 
 Functions (their sources are cited in ``exsum_oracle.c``):
 
 * ``brute``       -- O1, the Definition of included/excluded sums (Sec. 2), O(N^2).
 * ``scale_inc``   -- O2, nested window reductions (Sec. 2 reduction over a subtensor).
-* ``scale_exc``   -- O2, total minus included for ``+``; half-space cover for ``max``.
+* ``scale_exc``   -- O2, total minus included for ``+``; half-space cover for ``max``
+  and ``min``.
 * ``point_inc`` / ``point_exc`` / ``point_exc_direct`` -- one output at a time.
 * ``corners2d``   -- O3, 2-D corners cross-check (Sec. 1 / App. A idea).
 """
@@ -39,7 +40,7 @@ _SRC = os.path.join(_HERE, "exsum_oracle.c")
 _LIB_DEFAULT = os.path.join(_HERE, "liboracle.so")
 
 _DT = {"f32": 0, "f64": 1, "i32": 2, "i64": 3}
-_OP = {"sum": 0, "max": 1}
+_OP = {"sum": 0, "max": 1, "min": 2}
 
 _libs: dict = {}
 
@@ -70,8 +71,8 @@ def _bind(lib):
         "orc_point_inc_i64": [I, P, P, I, I, P, L, P, P],
         "orc_point_exc_direct_f64": [I, P, P, I, P, L, P, P],
         "orc_point_exc_direct_i64": [I, P, P, I, I, P, L, P, P],
-        "orc_point_exc_max_f64": [I, P, P, P, L, P, P],
-        "orc_point_exc_max_i64": [I, P, P, I, P, L, P, P],
+        "orc_point_exc_cover_f64": [I, P, P, I, P, L, P, P],
+        "orc_point_exc_cover_i64": [I, P, P, I, I, P, L, P, P],
         "orc_corners2d_f64": [L, L, L, L, I, P, P],
         "orc_corners2d_i64": [L, L, L, L, I, I, P, P],
     }
@@ -212,18 +213,19 @@ class Oracle:
 
     def point_exc(self, a, k, op, dtype, pts):
         """Excluded sums at ``pts``: total minus included for ``sum``, the
-        half-space cover for ``max``."""
+        half-space cover for ``max`` and ``min``."""
         d, n, kk, w = self._prep(a, k, op, dtype)
         pts = np.ascontiguousarray(pts, dtype=np.int64)
         p = self._p
-        if op == "max":
+        if op != "sum":
             out = np.empty(pts.shape[0], w.dtype)
             if w.dtype == np.float64:
-                rc = self.lib.orc_point_exc_max_f64(d, p(n), p(kk), p(w), pts.shape[0], p(pts), p(out))
+                rc = self.lib.orc_point_exc_cover_f64(d, p(n), p(kk), _OP[op], p(w),
+                                                      pts.shape[0], p(pts), p(out))
             else:
-                rc = self.lib.orc_point_exc_max_i64(d, p(n), p(kk), _DT[dtype], p(w),
-                                                    pts.shape[0], p(pts), p(out))
-            self._check(rc, "point_exc_max")
+                rc = self.lib.orc_point_exc_cover_i64(d, p(n), p(kk), _OP[op], _DT[dtype], p(w),
+                                                      pts.shape[0], p(pts), p(out))
+            self._check(rc, "point_exc_cover")
             return out
         inc = self.point_inc(a, k, op, dtype, pts)
         if w.dtype == np.float64:

@@ -26,11 +26,12 @@
  *
  * Element domains.  Inputs are passed widened:
  *   - floating dtypes (f32, f64) as double; + is evaluated in double (an FP64
- *     reference for f32 inputs), max is exact.  Identity: 0 for +, -inf for max.
+ *     reference for f32 inputs), max and min are exact.  Identity: 0 for +,
+ *     -inf for max, +inf for min.
  *   - integer dtypes (i32, i64) as int64; + wraps modulo 2^64 (done in uint64)
  *     and, for i32, the result is reduced modulo 2^32 at the end, which equals
  *     the modulo-2^32 sum whatever the order of the additions.  Identity: 0 for
- *     +, the dtype's minimum for max.
+ *     +, the dtype's minimum for max, its maximum for min.
  *
  * Functions:
  *   O1  orc_brute_*       the definition by brute force: O(N^2).
@@ -40,10 +41,11 @@
  *       orc_scale_exc_*   excluded sums: for + as total minus included (the
  *                         box and its complement partition U, and the oracle's
  *                         domains -- doubles, integers mod 2^w -- have an
- *                         inverse); for max as a union of half-spaces (a point
- *                         is outside the box iff some coordinate is below x_i
- *                         or at/after x_i + k_i; max is idempotent so the
- *                         overlap of half-spaces does not matter).  O(d N).
+ *                         inverse); for max and min as a union of half-spaces
+ *                         (a point is outside the box iff some coordinate is
+ *                         below x_i or at/after x_i + k_i; max and min are
+ *                         idempotent, so the overlap of half-spaces does not
+ *                         matter).  O(d N).
  *       orc_point_*       one output at a time (sampled checks at full size).
  *   O3  orc_corners2d_*   2-D cross-check after the corners idea (Sec. 1,
  *                         "Corners Algorithm for Strong Excluded Sums"; App. A):
@@ -63,20 +65,29 @@
 #endif
 
 enum { ORC_F32 = 0, ORC_F64 = 1, ORC_I32 = 2, ORC_I64 = 3 };
-enum { ORC_SUM = 0, ORC_MAX = 1 };
+enum { ORC_SUM = 0, ORC_MAX = 1, ORC_MIN = 2 };
 #define ORC_MAX_RANK 8
 
 /* ------------------------------------------------------------------------ */
 /* The monoid (Sec. 1: an associative operator with an identity).           */
 /* ------------------------------------------------------------------------ */
 
-static double f_ident(int op) { return op == ORC_SUM ? 0.0 : -INFINITY; }
+static double f_ident(int op) {
+    if (op == ORC_SUM) return 0.0;
+    return op == ORC_MAX ? -INFINITY : INFINITY;
+}
 static double f_op(int op, double a, double b) {
     if (op == ORC_SUM) return a + b;
-    return a > b ? a : b;
+    if (op == ORC_MAX) return a > b ? a : b;
+    return a < b ? a : b;
 }
 static int64_t i_ident(int op, int dtype) {
     if (op == ORC_SUM) return 0;
+#if ORC_MUTANT == 6
+    if (op == ORC_MIN) return 0; /* planted mistake: wrong identity for min */
+#else
+    if (op == ORC_MIN) return dtype == ORC_I32 ? (int64_t)INT32_MAX : INT64_MAX;
+#endif
 #if ORC_MUTANT == 2
     (void)dtype;
     return 0; /* planted mistake: wrong identity for max */
@@ -86,7 +97,8 @@ static int64_t i_ident(int op, int dtype) {
 }
 static int64_t i_op(int op, int64_t a, int64_t b) {
     if (op == ORC_SUM) return (int64_t)((uint64_t)a + (uint64_t)b); /* wraps */
-    return a > b ? a : b;
+    if (op == ORC_MAX) return a > b ? a : b;
+    return a < b ? a : b;
 }
 /* Final reduction of an integer + result to the dtype's width (mod 2^32). */
 static int64_t i_fix(int op, int dtype, int64_t v) {
@@ -247,39 +259,40 @@ int orc_scale_inc_i64(int d, const int64_t *n, const int64_t *k, int op, int dty
 /* O2 excluded.                                                              */
 /* ------------------------------------------------------------------------ */
 
-/* Slab reductions for the max cover: slab[j][t] = max of A over y_j == t.
- * pre[j][t] = max over y_j < t (t = 0..n_j), suf[j][t] = max over y_j >= t. */
+/* Slab reductions for the half-space cover (op max or min):
+ * slab[t] = op of A over y_j == t, pre[j][t] = op over y_j < t (t = 0..n_j),
+ * suf[j][t] = op over y_j >= t. */
 typedef struct { double *pre[ORC_MAX_RANK], *suf[ORC_MAX_RANK]; } f_cover;
 typedef struct { int64_t *pre[ORC_MAX_RANK], *suf[ORC_MAX_RANK]; } i_cover;
 
-static int f_cover_build(int d, const int64_t *n, int64_t N, const double *a, f_cover *c) {
+static int f_cover_build(int d, const int64_t *n, int64_t N, int op, const double *a,
+                         f_cover *c) {
     memset(c, 0, sizeof(*c));
+    const double e = f_ident(op);
     for (int j = 0; j < d; ++j) {
         c->pre[j] = (double *)malloc(sizeof(double) * (size_t)(n[j] + 1));
         c->suf[j] = (double *)malloc(sizeof(double) * (size_t)(n[j] + 1));
         if (!c->pre[j] || !c->suf[j]) return -2;
         double *slab = c->suf[j]; /* reuse as scratch */
-        for (int64_t t = 0; t <= n[j]; ++t) slab[t] = -INFINITY;
+        for (int64_t t = 0; t <= n[j]; ++t) slab[t] = e;
         int64_t inner = 1;
         for (int m = j + 1; m < d; ++m) inner *= n[m];
         for (int64_t p = 0; p < N; ++p) {
             int64_t t = (p / inner) % n[j];
-            if (a[p] > slab[t]) slab[t] = a[p];
+            slab[t] = f_op(op, slab[t], a[p]);
         }
-        c->pre[j][0] = -INFINITY;
-        for (int64_t t = 0; t < n[j]; ++t)
-            c->pre[j][t + 1] = c->pre[j][t] > slab[t] ? c->pre[j][t] : slab[t];
-        /* suffix in place: suf[t] = max over y_j >= t; suf[n_j] = -inf */
-        for (int64_t t = n[j] - 1; t >= 0; --t)
-            slab[t] = slab[t] > slab[t + 1] ? slab[t] : slab[t + 1];
+        c->pre[j][0] = e;
+        for (int64_t t = 0; t < n[j]; ++t) c->pre[j][t + 1] = f_op(op, c->pre[j][t], slab[t]);
+        /* suffix in place: suf[t] = op over y_j >= t; suf[n_j] = e */
+        for (int64_t t = n[j] - 1; t >= 0; --t) slab[t] = f_op(op, slab[t], slab[t + 1]);
     }
     return 0;
 }
 
-static int i_cover_build(int d, const int64_t *n, int64_t N, int dtype,
+static int i_cover_build(int d, const int64_t *n, int64_t N, int op, int dtype,
                          const int64_t *a, i_cover *c) {
     memset(c, 0, sizeof(*c));
-    const int64_t e = i_ident(ORC_MAX, dtype);
+    const int64_t e = i_ident(op, dtype);
     for (int j = 0; j < d; ++j) {
         c->pre[j] = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n[j] + 1));
         c->suf[j] = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n[j] + 1));
@@ -290,47 +303,45 @@ static int i_cover_build(int d, const int64_t *n, int64_t N, int dtype,
         for (int m = j + 1; m < d; ++m) inner *= n[m];
         for (int64_t p = 0; p < N; ++p) {
             int64_t t = (p / inner) % n[j];
-            if (a[p] > slab[t]) slab[t] = a[p];
+            slab[t] = i_op(op, slab[t], a[p]);
         }
         c->pre[j][0] = e;
-        for (int64_t t = 0; t < n[j]; ++t)
-            c->pre[j][t + 1] = c->pre[j][t] > slab[t] ? c->pre[j][t] : slab[t];
-        for (int64_t t = n[j] - 1; t >= 0; --t)
-            slab[t] = slab[t] > slab[t + 1] ? slab[t] : slab[t + 1];
+        for (int64_t t = 0; t < n[j]; ++t) c->pre[j][t + 1] = i_op(op, c->pre[j][t], slab[t]);
+        for (int64_t t = n[j] - 1; t >= 0; --t) slab[t] = i_op(op, slab[t], slab[t + 1]);
     }
     return 0;
 }
 
-/* Excluded max at x: the complement of box(x) is the union over axes j of
- * {y_j < x_j} and {y_j >= x_j + k_j}. */
-static double f_cover_at(int d, const int64_t *n, const int64_t *k, const f_cover *c,
+/* Excluded max / min at x: the complement of box(x) is the union over axes j
+ * of {y_j < x_j} and {y_j >= x_j + k_j}. */
+static double f_cover_at(int d, const int64_t *n, const int64_t *k, int op, const f_cover *c,
                          const int64_t *x) {
-    double m = -INFINITY;
+    double m = f_ident(op);
     for (int j = 0; j < d; ++j) {
         double lo = c->pre[j][x[j]];
         int64_t hi_start = x[j] + k[j];
         if (hi_start > n[j]) hi_start = n[j];
 #if ORC_MUTANT == 5
-        double hi = -INFINITY; (void)hi_start; /* planted: suffix half-space dropped */
+        double hi = f_ident(op); (void)hi_start; /* planted: suffix half-space dropped */
 #else
         double hi = c->suf[j][hi_start];
 #endif
-        if (lo > m) m = lo;
-        if (hi > m) m = hi;
+        m = f_op(op, m, lo);
+        m = f_op(op, m, hi);
     }
     return m;
 }
 
-static int64_t i_cover_at(int d, const int64_t *n, const int64_t *k, int dtype,
+static int64_t i_cover_at(int d, const int64_t *n, const int64_t *k, int op, int dtype,
                           const i_cover *c, const int64_t *x) {
-    int64_t m = i_ident(ORC_MAX, dtype);
+    int64_t m = i_ident(op, dtype);
     for (int j = 0; j < d; ++j) {
         int64_t lo = c->pre[j][x[j]];
         int64_t hi_start = x[j] + k[j];
         if (hi_start > n[j]) hi_start = n[j];
         int64_t hi = c->suf[j][hi_start];
-        if (lo > m) m = lo;
-        if (hi > m) m = hi;
+        m = i_op(op, m, lo);
+        m = i_op(op, m, hi);
     }
     return m;
 }
@@ -355,12 +366,12 @@ int orc_scale_exc_f64(int d, const int64_t *n, const int64_t *k, int op,
         return 0;
     }
     f_cover c;
-    if (f_cover_build(d, n, N, a, &c)) { f_cover_free(&c); return -2; }
+    if (f_cover_build(d, n, N, op, a, &c)) { f_cover_free(&c); return -2; }
     #pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < N; ++p) {
         int64_t x[ORC_MAX_RANK];
         unflatten(d, n, p, x);
-        exc[p] = f_cover_at(d, n, k, &c, x);
+        exc[p] = f_cover_at(d, n, k, op, &c, x);
     }
     f_cover_free(&c);
     return 0;
@@ -379,12 +390,12 @@ int orc_scale_exc_i64(int d, const int64_t *n, const int64_t *k, int op, int dty
         return 0;
     }
     i_cover c;
-    if (i_cover_build(d, n, N, dtype, a, &c)) { i_cover_free(&c); return -2; }
+    if (i_cover_build(d, n, N, op, dtype, a, &c)) { i_cover_free(&c); return -2; }
     #pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < N; ++p) {
         int64_t x[ORC_MAX_RANK];
         unflatten(d, n, p, x);
-        exc[p] = i_cover_at(d, n, k, dtype, &c, x);
+        exc[p] = i_cover_at(d, n, k, op, dtype, &c, x);
     }
     i_cover_free(&c);
     return 0;
@@ -502,32 +513,32 @@ int orc_point_exc_direct_i64(int d, const int64_t *n, const int64_t *k, int op, 
     return 0;
 }
 
-/* Excluded max at each point via the half-space cover (O(dN) set-up). */
-int orc_point_exc_max_f64(int d, const int64_t *n, const int64_t *k,
-                          const double *a, int64_t npts, const int64_t *pts, double *out) {
+/* Excluded max / min at each point via the half-space cover (O(dN) set-up). */
+int orc_point_exc_cover_f64(int d, const int64_t *n, const int64_t *k, int op,
+                            const double *a, int64_t npts, const int64_t *pts, double *out) {
     int64_t N;
-    if (check_args(d, n, k, &N)) return -1;
+    if (check_args(d, n, k, &N) || op == ORC_SUM) return -1;
     f_cover c;
-    if (f_cover_build(d, n, N, a, &c)) { f_cover_free(&c); return -2; }
+    if (f_cover_build(d, n, N, op, a, &c)) { f_cover_free(&c); return -2; }
     for (int64_t s = 0; s < npts; ++s) {
         int64_t x[ORC_MAX_RANK];
         unflatten(d, n, pts[s], x);
-        out[s] = f_cover_at(d, n, k, &c, x);
+        out[s] = f_cover_at(d, n, k, op, &c, x);
     }
     f_cover_free(&c);
     return 0;
 }
 
-int orc_point_exc_max_i64(int d, const int64_t *n, const int64_t *k, int dtype,
-                          const int64_t *a, int64_t npts, const int64_t *pts, int64_t *out) {
+int orc_point_exc_cover_i64(int d, const int64_t *n, const int64_t *k, int op, int dtype,
+                            const int64_t *a, int64_t npts, const int64_t *pts, int64_t *out) {
     int64_t N;
-    if (check_args(d, n, k, &N)) return -1;
+    if (check_args(d, n, k, &N) || op == ORC_SUM) return -1;
     i_cover c;
-    if (i_cover_build(d, n, N, dtype, a, &c)) { i_cover_free(&c); return -2; }
+    if (i_cover_build(d, n, N, op, dtype, a, &c)) { i_cover_free(&c); return -2; }
     for (int64_t s = 0; s < npts; ++s) {
         int64_t x[ORC_MAX_RANK];
         unflatten(d, n, pts[s], x);
-        out[s] = i_cover_at(d, n, k, dtype, &c, x);
+        out[s] = i_cover_at(d, n, k, op, dtype, &c, x);
     }
     i_cover_free(&c);
     return 0;

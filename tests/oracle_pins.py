@@ -10,10 +10,11 @@ itself):
   * closed forms (all-ones and one-hot tensors);
   * textbook routines written independently in numpy: the summed-area table
     (Sec. 1, "Summed-area Table for Weak Excluded Sums") for +, a sliding
-    window maximum on an identity-padded array for max, numpy masks over the
-    complement of each box for excluded sums;
+    window maximum (minimum) on an identity-padded array for max (min), numpy
+    masks over the complement of each box for excluded sums;
   * invariants: with + on integers, included plus excluded equals the total;
-    with max, the larger of the two equals the global maximum; the 1-D
+    with max (min), the larger (smaller) of the two equals the global maximum
+    (minimum); the 1-D
     excluded sum is prefix(x-1) op suffix(x+k); permuting axes permutes the
     result; k = n leaves an empty complement at the origin.
 """
@@ -26,12 +27,8 @@ from numpy.lib.stride_tricks import sliding_window_view
 
 I32_MIN = np.iinfo(np.int32).min
 I64_MIN = np.iinfo(np.int64).min
-
-
-def _ident(op, dtype):
-    if op == "sum":
-        return 0
-    return -np.inf if dtype in ("f32", "f64") else (I32_MIN if dtype == "i32" else I64_MIN)
+I32_MAX = np.iinfo(np.int32).max
+I64_MAX = np.iinfo(np.int64).max
 
 
 # --------------------------------------------------------------------------
@@ -48,17 +45,26 @@ def pin_hand_1d(o):
                1 + 2 + 3 + 4 + 5, 1 + 2 + 3 + 4 + 5 + 6, 1 + 2 + 3 + 4 + 5 + 6 + 7]
     inc_max = [4, 5, 6, 7, 8, 8, 8, 8]
     exc_max = [8, 8, 8, 8, 4, 5, 6, 7]
+    # min: the box at x starts with its smallest element; every complement but
+    # the first holds A[0] = 1
+    inc_min = [1, 2, 3, 4, 5, 6, 7, 8]
+    exc_min = [5, 1, 1, 1, 1, 1, 1, 1]
     for fn in ("brute", "scale"):
         for dt in ("i64", "i32", "f64", "f32"):
             i, e = getattr(o, fn)(a, [4], "sum", dt)
             assert np.array_equal(i, inc_sum) and np.array_equal(e, exc_sum), (fn, dt, i, e)
             i, e = getattr(o, fn)(a, [4], "max", dt)
             assert np.array_equal(i, inc_max) and np.array_equal(e, exc_max), (fn, dt, i, e)
+            i, e = getattr(o, fn)(a, [4], "min", dt)
+            assert np.array_equal(i, inc_min) and np.array_equal(e, exc_min), (fn, dt, i, e)
     pts = np.arange(8)
     assert np.array_equal(o.point_inc(a, [4], "sum", "i64", pts), inc_sum)
     assert np.array_equal(o.point_exc(a, [4], "sum", "i64", pts), exc_sum)
     assert np.array_equal(o.point_exc_direct(a, [4], "sum", "i64", pts), exc_sum)
     assert np.array_equal(o.point_exc(a, [4], "max", "i64", pts), exc_max)
+    assert np.array_equal(o.point_inc(a, [4], "min", "i64", pts), inc_min)
+    assert np.array_equal(o.point_exc(a, [4], "min", "i64", pts), exc_min)
+    assert np.array_equal(o.point_exc_direct(a, [4], "min", "i64", pts), exc_min)
 
 
 def pin_hand_2d(o):
@@ -71,14 +77,21 @@ def pin_hand_2d(o):
     inc_max = np.array([[6, 7, 8, 8], [10, 11, 12, 12], [10, 11, 12, 12]])
     # 12 sits at (2, 3): only the boxes at (1,2), (1,3), (2,2), (2,3) hold it
     exc_max = np.array([[12, 12, 12, 12], [12, 12, 10, 11], [12, 12, 10, 11]])
+    # min: each box starts at its smallest element; 1 sits at (0, 0), so only
+    # the box at (0, 0) holds it, and its complement's smallest is 3
+    inc_min = a.copy()
+    exc_min = np.array([[3, 1, 1, 1], [1, 1, 1, 1], [1, 1, 1, 1]])
     for dt in ("i64", "f64"):
         for fn in ("brute", "scale"):
             i, e = getattr(o, fn)(a, [2, 2], "sum", dt)
             assert np.array_equal(i, inc_sum) and np.array_equal(e, exc_sum), (fn, dt)
             i, e = getattr(o, fn)(a, [2, 2], "max", dt)
             assert np.array_equal(i, inc_max) and np.array_equal(e, exc_max), (fn, dt)
+            i, e = getattr(o, fn)(a, [2, 2], "min", dt)
+            assert np.array_equal(i, inc_min) and np.array_equal(e, exc_min), (fn, dt)
         assert np.array_equal(o.corners2d(a, [2, 2], "sum", dt), exc_sum)
         assert np.array_equal(o.corners2d(a, [2, 2], "max", dt), exc_max)
+        assert np.array_equal(o.corners2d(a, [2, 2], "min", dt), exc_min)
 
 
 # --------------------------------------------------------------------------
@@ -145,20 +158,20 @@ def sat_included_sum(a, k):
     return out
 
 
-def window_max_included(a, k, ident):
-    """Sliding-window maximum over an identity-padded array."""
+def window_max_included(a, k, ident, reduce=np.max):
+    """Sliding-window maximum (or ``reduce``) over an identity-padded array."""
     a = np.asarray(a)
     pad = [(0, kk - 1) for kk in k]
     p = np.pad(a, pad, constant_values=ident)
     w = sliding_window_view(p, tuple(k))
-    return w.max(axis=tuple(range(a.ndim, 2 * a.ndim)))
+    return reduce(w, axis=tuple(range(a.ndim, 2 * a.ndim)))
 
 
 def masked_excluded(a, k, op, ident):
     """For each cell, reduce A over a boolean mask of the complement of its box."""
     a = np.asarray(a)
     grids = np.meshgrid(*[np.arange(s) for s in a.shape], indexing="ij")
-    out = np.empty(a.shape, dtype=a.dtype if op == "max" else np.int64)
+    out = np.empty(a.shape, dtype=np.int64 if op == "sum" else a.dtype)
     for x in itertools.product(*[range(s) for s in a.shape]):
         inside = np.ones(a.shape, bool)
         for ax in range(a.ndim):
@@ -166,8 +179,10 @@ def masked_excluded(a, k, op, ident):
         vals = a[~inside]
         if op == "sum":
             out[x] = vals.astype(np.int64).sum()
-        else:
+        elif op == "max":
             out[x] = vals.max() if vals.size else ident
+        else:
+            out[x] = vals.min() if vals.size else ident
     return out
 
 
@@ -191,11 +206,20 @@ def pin_textbook(o):
             i, e = getattr(o, fn)(a, k, "max", "i64")
             assert np.array_equal(i, wm), (fn, "max", shape, k)
             assert np.array_equal(e, me), (fn, "max", shape, k)
+        wn = window_max_included(a, k, I64_MAX, np.min)
+        mn = masked_excluded(a, k, "min", I64_MAX)
+        for fn in ("brute", "scale"):
+            i, e = getattr(o, fn)(a, k, "min", "i64")
+            assert np.array_equal(i, wn), (fn, "min", shape, k)
+            assert np.array_equal(e, mn), (fn, "min", shape, k)
         # floats: the window max is exact; the masked + is exact on integers
         af = a.astype(np.float64) / 4.0
         i, e = o.brute(af, k, "max", "f64")
         assert np.array_equal(i, window_max_included(af, k, -np.inf))
         assert np.array_equal(e, masked_excluded(af, k, "max", -np.inf))
+        i, e = o.scale(af, k, "min", "f64")
+        assert np.array_equal(i, window_max_included(af, k, np.inf, np.min))
+        assert np.array_equal(e, masked_excluded(af, k, "min", np.inf))
         i, e = o.scale(af, k, "sum", "f64")
         assert np.array_equal(i, sat / 4.0) and np.array_equal(e, (tot - sat) / 4.0)
 
@@ -229,6 +253,8 @@ def pin_invariants(o):
         assert np.all(i + e == a.sum())
         i, e = o.brute(a, k, "max", "i64")
         assert np.all(np.maximum(i, e) == a.max())
+        i, e = o.scale(a, k, "min", "i64")
+        assert np.all(np.minimum(i, e) == a.min())
         # permuting axes permutes the outputs
         perm = tuple(reversed(range(len(shape))))
         kp = tuple(k[p] for p in perm)
@@ -251,12 +277,21 @@ def pin_invariants(o):
         for fn in ("brute", "scale"):
             _, e = getattr(o, fn)(a, [kk], "max", "i64")
             assert np.array_equal(e, expect), (fn, "max", n, kk)
+        premin = np.concatenate([[I64_MAX], np.minimum.accumulate(a)])
+        sufmin = np.concatenate([np.minimum.accumulate(a[::-1])[::-1], [I64_MAX]])
+        expect = np.minimum(premin[x], sufmin[np.minimum(x + kk, n)])
+        for fn in ("brute", "scale"):
+            _, e = getattr(o, fn)(a, [kk], "min", "i64")
+            assert np.array_equal(e, expect), (fn, "min", n, kk)
     # k = n: the box at the origin covers the tensor, so its complement is empty
-    for dt, ident in (("i32", I32_MIN), ("i64", I64_MIN), ("f64", -np.inf)):
+    for dt, ident, ident_min in (("i32", I32_MIN, I32_MAX), ("i64", I64_MIN, I64_MAX),
+                                 ("f64", -np.inf, np.inf)):
         a = rng.integers(-5, 6, size=(3, 4)).astype(np.float64 if dt == "f64" else np.int64)
         for fn in ("brute", "scale"):
             _, e = getattr(o, fn)(a, [3, 4], "max", dt)
             assert e[0, 0] == ident, (fn, dt, e[0, 0])
+            _, e = getattr(o, fn)(a, [3, 4], "min", dt)
+            assert e[0, 0] == ident_min, (fn, dt, e[0, 0])
             _, e = getattr(o, fn)(a, [3, 4], "sum", dt)
             assert e[0, 0] == 0, (fn, dt)
 

@@ -25,7 +25,7 @@ AGREE_CASES = [
 
 @pytest.mark.parametrize("shape,k", AGREE_CASES)
 @pytest.mark.parametrize("dtype", ["f32", "f64", "i32", "i64"])
-@pytest.mark.parametrize("op", ["sum", "max"])
+@pytest.mark.parametrize("op", ["sum", "max", "min"])
 def test_brute_scale_point_agree(orc, shape, k, dtype, op):
     rng = np.random.default_rng(abs(hash((shape, k, dtype, op))) % 2**32)
     if dtype in ("f32", "f64"):
@@ -67,7 +67,8 @@ def test_rejects_bad_args(orc):
 #   1 closed box (off by one at the high edge)   2 wrong identity for max
 #   3 axes reversed in the point oracle          4 no wrap of i32 sums
 #   5 suffix half-space dropped in the max cover
-@pytest.mark.parametrize("mutant", [1, 2, 3, 4, 5])
+#   6 wrong identity for integer min
+@pytest.mark.parametrize("mutant", [1, 2, 3, 4, 5, 6])
 def test_pins_catch_planted_mistakes(mutant):
     with tempfile.TemporaryDirectory() as td:
         path = oracle.build(mutant=mutant, out=os.path.join(td, f"m{mutant}.so"))
