@@ -12,7 +12,7 @@
  *     excluded sum  Exc(x) = op over every element of A outside that box
  * (coordinates past the end of the tensor contribute e; Sec. 1 and the colon
  * notation of Sec. 2).  Both are the "strong" problems: no inverse of op is
- * used, so max works as well as +.  Included sums follow the bidirectional
+ * used, so max and min work as well as +.  Included sums follow the bidirectional
  * box-sum (BDBS) algorithm (Sec. 3); excluded sums follow the box-complement
  * algorithm (Secs. 4-5: Theorem "Recursive Box-complement", Corollary
  * "Excluded-sum Components").
@@ -23,9 +23,11 @@
  *     contiguous.  Outputs have the input's shape and element type (Sec. 2:
  *     the output is a tensor over the same monoid).
  *   - Element types and operators: + on f32, f64, i32, i64 (integer + wraps
- *     modulo 2^32 / 2^64, so it is associative and commutative); max on all
- *     four.  Identity e: 0 for +, -inf for float max, the type's minimum for
- *     integer max (the value of an excluded sum whose complement is empty).
+ *     modulo 2^32 / 2^64, so it is associative and commutative); max and min
+ *     on all four (the problem is stated over any commutative monoid, Sec. 2).
+ *     Identity e: 0 for +, -inf / +inf for float max / min, the type's
+ *     minimum / maximum for integer max / min (the value of an excluded sum
+ *     whose complement is empty).
  *   - Preconditions: 1 <= d <= EXS_MAX_RANK; dims[i] >= 1; 1 <= box[i] <= dims[i]
  *     (Sec. 1 requires k_i <= n_i); the product of dims fits in int64.
  *   - Pointers named *_dev are device pointers (hipMalloc / PyTorch CUDA
@@ -63,7 +65,7 @@ typedef enum {
 } exs_status;
 
 typedef enum { EXS_F32 = 0, EXS_F64 = 1, EXS_I32 = 2, EXS_I64 = 3 } exs_dtype;
-typedef enum { EXS_SUM = 0, EXS_MAX = 1 } exs_op;
+typedef enum { EXS_SUM = 0, EXS_MAX = 1, EXS_MIN = 2 } exs_op;
 
 /* mode bit-mask */
 #define EXS_INCLUDED 1u
@@ -74,7 +76,7 @@ typedef enum { EXS_SUM = 0, EXS_MAX = 1 } exs_op;
  * measures both).  Exact for the integer types (wrapping); for floating point
  * the total is accumulated in FP64 and the subtraction is done in the element
  * type, so cells whose excluded sum nearly cancels lose relative accuracy.
- * With op EXS_MAX: EXS_EUNSUPPORTED (max has no inverse).  Not accepted by
+ * With op EXS_MAX or EXS_MIN: EXS_EUNSUPPORTED (no inverse).  Not accepted by
  * exs_batch_create (EXS_EUNSUPPORTED). */
 #define EXS_WEAK 4u
 

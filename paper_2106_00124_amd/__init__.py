@@ -31,7 +31,7 @@ def _dtype_code(t):
         raise ExsError(1, f"unsupported dtype {t}") from None
 
 
-_OPS = {"sum": _lib.SUM, "+": _lib.SUM, "max": _lib.MAX}
+_OPS = {"sum": _lib.SUM, "+": _lib.SUM, "max": _lib.MAX, "min": _lib.MIN}
 _MODES = {"inc": _lib.INCLUDED, "included": _lib.INCLUDED, "exc": _lib.EXCLUDED,
           "excluded": _lib.EXCLUDED, "both": _lib.INCLUDED | _lib.EXCLUDED,
           # weak excluded sums (total - included), + only

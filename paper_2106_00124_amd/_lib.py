@@ -14,7 +14,7 @@ LIB_PATH = os.environ.get("EXSUM_LIB", os.path.join(HERE, "libexsum.so"))
 
 MAX_RANK = 8
 F32, F64, I32, I64 = 0, 1, 2, 3
-SUM, MAX = 0, 1
+SUM, MAX, MIN = 0, 1, 2
 INCLUDED, EXCLUDED, WEAK = 1, 2, 4
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE, EAGAIN, ENOTREADY, ENOTFOUND = range(8)
 

@@ -55,7 +55,8 @@ exs_status validate_job(const exs_job* job, bool check_ptrs) {
     if (job->d < 1 || job->d > EXS_MAX_RANK)
         return set_error(EXS_EINVAL, "rank d must be in 1..8");
     if (dtype_size(job->dtype) == 0) return set_error(EXS_EINVAL, "unknown dtype");
-    if (job->op != EXS_SUM && job->op != EXS_MAX) return set_error(EXS_EINVAL, "unknown op");
+    if (job->op != EXS_SUM && job->op != EXS_MAX && job->op != EXS_MIN)
+        return set_error(EXS_EINVAL, "unknown op");
     if (job->mode == 0 || (job->mode & ~(EXS_INCLUDED | EXS_EXCLUDED | EXS_WEAK)))
         return set_error(EXS_EINVAL, "mode must be EXS_INCLUDED and/or EXS_EXCLUDED [| EXS_WEAK]");
     if (job->mode & EXS_WEAK) {
@@ -63,7 +64,7 @@ exs_status validate_job(const exs_job* job, bool check_ptrs) {
             return set_error(EXS_EINVAL, "EXS_WEAK needs EXS_EXCLUDED");
         if (job->op != EXS_SUM)
             return set_error(EXS_EUNSUPPORTED,
-                             "weak excluded sums subtract, and max has no inverse");
+                             "weak excluded sums subtract; only + has an inverse");
     }
     __int128 N = 1;
     for (int i = 0; i < job->d; ++i) {
@@ -218,7 +219,11 @@ static exs_status run_dtype(const exs_job* job, Arena& ar, hipStream_t st) {
         EagerSink<T, OpSum> sink{st};
         return plan_job<T>(job, ar, sink);
     }
-    EagerSink<T, OpMax> sink{st};
+    if (job->op == EXS_MAX) {
+        EagerSink<T, OpMax> sink{st};
+        return plan_job<T>(job, ar, sink);
+    }
+    EagerSink<T, OpMin> sink{st};
     return plan_job<T>(job, ar, sink);
 }
 

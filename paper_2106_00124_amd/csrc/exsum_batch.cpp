@@ -210,22 +210,21 @@ static exs_status plan_into(const exs_job* job, Arena& ar, std::vector<Rec>* out
     return plan_job<T>(job, ar, sink);
 }
 
+template <typename T>
+static exs_status plan_op(const exs_job* job, Arena& ar, std::vector<Rec>* out,
+                          const TuneCfg& cfg) {
+    if (job->op == EXS_SUM) return plan_into<T, OpSum>(job, ar, out, cfg);
+    if (job->op == EXS_MAX) return plan_into<T, OpMax>(job, ar, out, cfg);
+    return plan_into<T, OpMin>(job, ar, out, cfg);
+}
+
 static exs_status plan_any(const exs_job* job, Arena& ar, std::vector<Rec>* out,
                            const TuneCfg& cfg) {
-    const bool sum = job->op == EXS_SUM;
     switch (job->dtype) {
-        case EXS_F32:
-            return sum ? plan_into<float, OpSum>(job, ar, out, cfg)
-                       : plan_into<float, OpMax>(job, ar, out, cfg);
-        case EXS_F64:
-            return sum ? plan_into<double, OpSum>(job, ar, out, cfg)
-                       : plan_into<double, OpMax>(job, ar, out, cfg);
-        case EXS_I32:
-            return sum ? plan_into<int, OpSum>(job, ar, out, cfg)
-                       : plan_into<int, OpMax>(job, ar, out, cfg);
-        case EXS_I64:
-            return sum ? plan_into<long long, OpSum>(job, ar, out, cfg)
-                       : plan_into<long long, OpMax>(job, ar, out, cfg);
+        case EXS_F32: return plan_op<float>(job, ar, out, cfg);
+        case EXS_F64: return plan_op<double>(job, ar, out, cfg);
+        case EXS_I32: return plan_op<int>(job, ar, out, cfg);
+        case EXS_I64: return plan_op<long long>(job, ar, out, cfg);
     }
     return set_error(EXS_EINVAL, "unknown dtype");
 }

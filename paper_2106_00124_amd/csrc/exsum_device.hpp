@@ -68,6 +68,29 @@ template <> __device__ __forceinline__ long long OpMax::id<long long>() {
     return (long long)0x8000000000000000ULL;
 }
 
+struct OpMin {
+    template <typename T> static __device__ __forceinline__ T id();
+    // min has no inverse; never called (weak excluded sums are + only)
+    template <typename T> static __device__ __forceinline__ T inverse(T a, T) { return a; }
+    // fp32 min as one v_min_f32, for the reason given for max
+    static __device__ __forceinline__ float apply(float a, float b) {
+        float r;
+        asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+        return r;
+    }
+    static __device__ __forceinline__ double apply(double a, double b) { return fmin(a, b); }
+    static __device__ __forceinline__ int apply(int a, int b) { return a < b ? a : b; }
+    static __device__ __forceinline__ long long apply(long long a, long long b) {
+        return a < b ? a : b;
+    }
+};
+template <> __device__ __forceinline__ float OpMin::id<float>() { return __builtin_inff(); }
+template <> __device__ __forceinline__ double OpMin::id<double>() { return __builtin_inf(); }
+template <> __device__ __forceinline__ int OpMin::id<int>() { return 0x7fffffff; }
+template <> __device__ __forceinline__ long long OpMin::id<long long>() {
+    return (long long)0x7fffffffffffffffULL;
+}
+
 __device__ __forceinline__ i64 gtid() {
     return (i64)blockIdx.x * (i64)blockDim.x + (i64)threadIdx.x;
 }

@@ -298,5 +298,9 @@ template void launch_long1d<int, OpSum>(const int*, int*, int*, i64, i64, int*, 
                                         hipStream_t);
 template void launch_long1d<int, OpMax>(const int*, int*, int*, i64, i64, int*, int*, int*, int*,
                                         hipStream_t);
+template void launch_long1d<float, OpMin>(const float*, float*, float*, i64, i64, float*, float*,
+                                          float*, float*, hipStream_t);
+template void launch_long1d<int, OpMin>(const int*, int*, int*, i64, i64, int*, int*, int*, int*,
+                                        hipStream_t);
 
 }  // namespace exs

@@ -12,6 +12,7 @@ namespace exs {
 
 struct OpSum;
 struct OpMax;
+struct OpMin;
 
 // register bucket (power of two >= k, up to 64) of a box length; 0 = none
 inline int bucket_for(i64 k) {

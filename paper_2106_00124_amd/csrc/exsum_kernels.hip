@@ -579,6 +579,10 @@ template void launch_tail_scan<int, OpSum>(const int*, int*, int*, int*, i64, i6
                                            hipStream_t);
 template void launch_tail_scan<int, OpMax>(const int*, int*, int*, int*, i64, i64, i64, i64,
                                            hipStream_t);
+template void launch_tail_scan<float, OpMin>(const float*, float*, float*, float*, i64, i64, i64,
+                                             i64, hipStream_t);
+template void launch_tail_scan<int, OpMin>(const int*, int*, int*, int*, i64, i64, i64, i64,
+                                           hipStream_t);
 
 template <typename T, class Op>
 void launch_blockagg(const T* X, T* Ga, i64 n0, i64 M, i64 k0, i64 Q, hipStream_t st) {
@@ -678,5 +682,9 @@ EXS_INSTANTIATE(float, OpMax)
 EXS_INSTANTIATE(double, OpMax)
 EXS_INSTANTIATE(int, OpMax)
 EXS_INSTANTIATE(long long, OpMax)
+EXS_INSTANTIATE(float, OpMin)
+EXS_INSTANTIATE(double, OpMin)
+EXS_INSTANTIATE(int, OpMin)
+EXS_INSTANTIATE(long long, OpMin)
 
 }  // namespace exs

@@ -39,13 +39,20 @@ template void launch_plane_axis0<float, OpSum>(const float*, const float*, const
 template void launch_plane_axis0<float, OpMax>(const float*, const float*, const float*,
                                                const float*, float*, float*, i64, i64, i64, i64,
                                                i64, i64, i64, i64, hipStream_t);
+template void launch_plane_axis0<float, OpMin>(const float*, const float*, const float*,
+                                               const float*, float*, float*, i64, i64, i64, i64,
+                                               i64, i64, i64, i64, hipStream_t);
 template void launch_plane_bdbs<float, OpSum>(const float*, float*, i64, i64, i64, i64, i64,
                                              hipStream_t);
 template void launch_plane_bdbs<float, OpMax>(const float*, float*, i64, i64, i64, i64, i64,
                                              hipStream_t);
+template void launch_plane_bdbs<float, OpMin>(const float*, float*, i64, i64, i64, i64, i64,
+                                             hipStream_t);
 template void launch_plane_scan<float, OpSum>(const float*, const float*, float*, float*, float*, float*, i64, i64,
                                             i64, i64, i64, i64, i64, hipStream_t);
 template void launch_plane_scan<float, OpMax>(const float*, const float*, float*, float*, float*, float*, i64, i64,
+                                            i64, i64, i64, i64, i64, hipStream_t);
+template void launch_plane_scan<float, OpMin>(const float*, const float*, float*, float*, float*, float*, i64, i64,
                                             i64, i64, i64, i64, i64, hipStream_t);
 template void launch_plane_weak<float, OpSum>(const float*, float*, const float*, float*, i64, i64,
                                               i64, i64, i64, i64, i64, hipStream_t);

@@ -23,5 +23,9 @@ template void launch_row_axis0<int, OpSum>(const int*, const int*, const int*, c
                                            int*, i64, i64, i64, i64, i64, hipStream_t);
 template void launch_row_axis0<int, OpMax>(const int*, const int*, const int*, const int*, int*,
                                            int*, i64, i64, i64, i64, i64, hipStream_t);
+template void launch_row_axis0<float, OpMin>(const float*, const float*, const float*, const float*,
+                                             float*, float*, i64, i64, i64, i64, i64, hipStream_t);
+template void launch_row_axis0<int, OpMin>(const int*, const int*, const int*, const int*, int*,
+                                           int*, i64, i64, i64, i64, i64, hipStream_t);
 
 }  // namespace exs

@@ -101,7 +101,8 @@ template <typename T>
 static void launch_op(int op, int kind, int kb, const Step* steps, int nsteps, i64 total, int grid,
                       size_t lds, hipStream_t st) {
     if (op == EXS_SUM) launch_kind<T, OpSum>(kind, kb, steps, nsteps, total, grid, lds, st);
-    else launch_kind<T, OpMax>(kind, kb, steps, nsteps, total, grid, lds, st);
+    else if (op == EXS_MAX) launch_kind<T, OpMax>(kind, kb, steps, nsteps, total, grid, lds, st);
+    else launch_kind<T, OpMin>(kind, kb, steps, nsteps, total, grid, lds, st);
 }
 
 void launch_worklist(int dtype, int op, int kind, int kb, const void* steps, int nsteps, i64 total,

@@ -19,7 +19,7 @@ def torch_dtype(dt):
 def make_input(shape, dtype, seed, op):
     rng = np.random.default_rng(seed)
     if dtype in ("f32", "f64"):
-        if op == "max":
+        if op in ("max", "min"):
             # distinct nonzero values: no ties between +0 and -0
             n = int(np.prod(shape))
             v = (rng.permutation(n) + 1.0) * rng.choice([-1.0, 1.0], n) / n

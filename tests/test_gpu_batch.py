@@ -23,7 +23,7 @@ def _mixed_items(seed, count):
         shape = tuple(int(rng.integers(2, 40 if d >= 3 else 90)) for _ in range(d))
         box = tuple(int(rng.integers(1, n + 1)) for n in shape)
         dtype = ["f32", "i32", "f64", "i64"][t % 4]
-        op = ["sum", "max"][(t // 4) % 2]
+        op = ["sum", "max", "min"][(t // 4) % 3]
         mode = ["both", "exc", "inc"][t % 3]
         items.append((shape, box, dtype, op, mode, int(rng.integers(0, 2**31))))
     # a long box (two-sweep kernels) and a 1-element tensor
@@ -35,6 +35,7 @@ def _mixed_items(seed, count):
     # many blocks for few points (segmented block scans)
     items.append(((20000, 5), (3, 2), "f32", "sum", "both", 15))
     items.append(((60000,), (2,), "i32", "max", "exc", 16))
+    items.append(((50, 60, 70), (4, 5, 6), "f32", "min", "both", 17))
     return items
 
 
@@ -74,7 +75,7 @@ def test_batch_matches_oracle_and_plain(orc):
         # the plain call: identical for integers and max (order-free)
         pi, pe = P.run(x, box, op, mode)
         torch.cuda.synchronize()
-        if dt in ("i32", "i64") or op == "max":
+        if dt in ("i32", "i64") or op != "sum":
             if inc is not None:
                 assert np.array_equal(pi.cpu().numpy(), inc), what
             if exc is not None:

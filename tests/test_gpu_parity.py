@@ -52,8 +52,9 @@ CASES = [
     ((256, 64, 200), (2, 3, 64)),
 ]
 
-DTYPE_OPS = [("f32", "sum"), ("f32", "max"), ("f64", "sum"), ("f64", "max"),
-             ("i32", "sum"), ("i32", "max"), ("i64", "sum"), ("i64", "max")]
+DTYPE_OPS = [("f32", "sum"), ("f32", "max"), ("f32", "min"), ("f64", "sum"), ("f64", "max"),
+             ("f64", "min"), ("i32", "sum"), ("i32", "max"), ("i32", "min"), ("i64", "sum"),
+             ("i64", "max"), ("i64", "min")]
 
 
 @pytest.mark.parametrize("shape,box", CASES, ids=lambda v: "x".join(map(str, v)))
@@ -183,5 +184,6 @@ def test_weak_max_unsupported():
     import paper_2106_00124_amd as P
     from paper_2106_00124_amd import ExsError
     x = torch.zeros((8, 8), device="cuda")
-    with pytest.raises(ExsError, match="EUNSUPPORTED"):
-        P.run(x, (2, 2), "max", "weak")
+    for op in ("max", "min"):
+        with pytest.raises(ExsError, match="EUNSUPPORTED"):
+            P.run(x, (2, 2), op, "weak")

@@ -19,7 +19,7 @@ def _mix(seed, count):
         shape = tuple(int(rng.integers(3, 70 if d == 3 else 300)) for _ in range(d))
         box = tuple(int(rng.integers(1, min(64, n) + 1)) for n in shape)
         dtype = ["f32", "i32", "i64", "f32"][t % 4]
-        op = "max" if (t % 5 == 4 and dtype != "i64") else "sum"
+        op = "max" if (t % 5 == 4 and dtype != "i64") else ("min" if t % 7 == 3 else "sum")
         mode = ["exc", "both", "inc"][t % 3]
         items.append((shape, box, dtype, op, mode, 1000 + t))
     return items

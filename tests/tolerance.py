@@ -44,7 +44,7 @@ def check(got, ref, dtype, op, sigma=None, tol=None, what=""):
     got = np.asarray(got)
     ref = np.asarray(ref)
     assert got.shape == ref.shape, (got.shape, ref.shape)
-    if dtype in ("i32", "i64") or op == "max":
+    if dtype in ("i32", "i64") or op in ("max", "min"):
         if dtype in ("i32", "i64"):
             g = got.astype(np.int64)
             bad = np.nonzero(g != ref.astype(np.int64))[0] if g.ndim == 1 else \
