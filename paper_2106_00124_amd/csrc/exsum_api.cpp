@@ -155,6 +155,10 @@ struct EagerSink {
         launch_blockagg<T, Op>(X, Ga, n0, M, k0, Q, st);
     }
     bool small1d_ok(i64 n) const { return ex1d_small_ok(n); }
+    i64 tail_box_max() const { return tail_box_max_elems((int)sizeof(T)); }
+    void bdbs_tail(const T* in, T* out, i64 O, int m, const i64* n, const i64* k) {
+        launch_bdbs_tail<T, Op>(in, out, O, m, n, k, st);
+    }
     bool long1d_ok(i64 n, i64 k) const { return sizeof(T) == 4 && exs::long1d_ok(n, k); }
     void long1d(const T* A, T* exc, T* inc, i64 n, i64 k, T* Tt, T* Ut, T* CP, T* CS) {
         if constexpr (sizeof(T) == 4) launch_long1d<T, Op>(A, exc, inc, n, k, Tt, Ut, CP, CS, st);

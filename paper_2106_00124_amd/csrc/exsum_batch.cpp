@@ -59,6 +59,9 @@ struct ListSink {
     void row_axis0(const T*, const T*, const T*, const T*, T*, T*, i64, i64, i64, i64, i64) {}
     // the single-workgroup kernel for a short last level has no work-list form
     bool small1d_ok(i64) const { return false; }
+    // the staged multi-axis BDBS has no work-list form
+    i64 tail_box_max() const { return 0; }
+    void bdbs_tail(const T*, T*, i64, int, const i64*, const i64*) {}
     bool long1d_ok(i64, i64) const { return false; }
     void long1d(const T*, T*, T*, i64, i64, T*, T*, T*, T*) {}
     void ex1d_small(const T*, T*, i64, i64) {}

@@ -82,6 +82,12 @@ bool plane2_eligible(i64 NY, i64 NX, i64 ky, i64 kx, int es);
 template <typename T, class Op>
 void launch_plane_scan(const T* G, const T* Ga, T* PX, T* SX, T* R, T* A1, i64 Q, i64 MID,
                        i64 NY, i64 NX, i64 ky, i64 kx, i64 pxe, hipStream_t st);
+// BDBS along the last m axes in one pass, for trailing sub-tensors of at most
+// tail_box_max_elems(es) elements (n, k: the m extents and box sides)
+i64 tail_box_max_elems(int es);
+template <typename T, class Op>
+void launch_bdbs_tail(const T* in, T* out, i64 O, int m, const i64* n, const i64* k,
+                      hipStream_t st);
 // excluded and/or included sums of a long 1-D level in chunks (4-byte
 // elements, k <= 16): chunk totals, their scans, the chunk pass; the four
 // scratch arrays hold long1d_chunks(n, k) elements each (unused, and may be

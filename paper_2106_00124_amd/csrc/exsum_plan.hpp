@@ -52,14 +52,35 @@ inline i64 prod(const i64* v, int a, int b) {
 
 // Box-sum a rank-d tensor over axes last .. first (last axis first: the
 // innermost reduction of the nested definition in Sec. 2), ping-ponging
-// between wb[0] and wb[1].  Returns the result (src itself if no axis).
+// between wb[0] and wb[1].  Axes with k = 1 are skipped (BDBS with k = 1 is
+// the identity); when the axes end at the tensor's last axis, the trailing
+// ones that fit the sink's staged sub-tensor go in one pass.  Returns the
+// result (src itself if no axis).
 template <typename T, class Sink>
 static const T* filter_axes(const T* src, const i64* n, const i64* k, int d, int first, int last,
                             T* wb0, T* wb1, bool dry, Sink& sink) {
     const T* cur = src;
     T* wb[2] = {wb0, wb1};
     int which = 0;
-    for (int a = last; a >= first; --a) {
+    int a = last;
+    if (last == d - 1) {
+        int m = 0, busy = 0;
+        i64 S = 1;
+        while (last - m >= first && S * n[last - m] <= sink.tail_box_max()) {
+            S *= n[last - m];
+            busy += k[last - m] > 1;
+            ++m;
+        }
+        if (busy >= 2) {
+            T* dst = wb[which];
+            which ^= 1;
+            if (!dry) sink.bdbs_tail(cur, dst, prod(n, 0, d - m), m, n + d - m, k + d - m);
+            cur = dst;
+            a = last - m;
+        }
+    }
+    for (; a >= first; --a) {
+        if (k[a] == 1) continue;
         T* dst = wb[which];
         which ^= 1;
         if (!dry) sink.bdbs(cur, dst, prod(n, 0, a), n[a], prod(n, a + 1, d), k[a]);

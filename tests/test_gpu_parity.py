@@ -47,6 +47,10 @@ CASES = [
     ((5,), (5,)),
     ((2, 40000), (2, 16)),
     ((3, 3, 20000), (2, 2, 11)),
+    # trailing axes box-summed in one LDS-staged pass: all of them (3024
+    # elements), or the last two with the third by a separate pass
+    ((5, 6, 7, 8, 9), (2, 3, 2, 3, 4)),
+    ((40, 30, 20, 10), (3, 4, 5, 6)),
     # enough rows along the contiguous axis for the LDS-staged row kernel
     ((65536, 130), (3, 5)),
     ((256, 64, 200), (2, 3, 64)),
