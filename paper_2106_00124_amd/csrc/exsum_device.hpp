@@ -46,14 +46,13 @@ struct OpMax {
     template <typename T> static __device__ __forceinline__ T id();
     // max has no inverse; never called (weak excluded sums are + only)
     template <typename T> static __device__ __forceinline__ T inverse(T a, T) { return a; }
-    // fp32 max as one v_max_f32.  fmaxf would first quiet signalling NaNs in
-    // every operand read from memory (an extra v_max_f32 x, x, x each), which
-    // finite inputs do not need and which costs registers in the unrolled
-    // scans.
+    // fp32 max as the IEEE 754-2019 maximum (v_maximum3_f32 on gfx950): the
+    // same value as maxnum for the finite inputs the library takes, without
+    // the operand quieting that maxnum needs for every value read from memory
+    // (which cost registers in the unrolled scans), and, unlike inline
+    // assembly, free for the scheduler to move loads across.
     static __device__ __forceinline__ float apply(float a, float b) {
-        float r;
-        asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-        return r;
+        return __builtin_elementwise_maximum(a, b);
     }
     static __device__ __forceinline__ double apply(double a, double b) { return fmax(a, b); }
     static __device__ __forceinline__ int apply(int a, int b) { return a > b ? a : b; }
@@ -72,11 +71,9 @@ struct OpMin {
     template <typename T> static __device__ __forceinline__ T id();
     // min has no inverse; never called (weak excluded sums are + only)
     template <typename T> static __device__ __forceinline__ T inverse(T a, T) { return a; }
-    // fp32 min as one v_min_f32, for the reason given for max
+    // fp32 min as the IEEE 754-2019 minimum, for the reasons given for max
     static __device__ __forceinline__ float apply(float a, float b) {
-        float r;
-        asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-        return r;
+        return __builtin_elementwise_minimum(a, b);
     }
     static __device__ __forceinline__ double apply(double a, double b) { return fmin(a, b); }
     static __device__ __forceinline__ int apply(int a, int b) { return a < b ? a : b; }
