@@ -79,7 +79,9 @@ def test_config_d4_128x128x64x64_i32(orc):
 @pytest.mark.parametrize("shape,box", [
     ((64, 4096, 4096), (16, 16, 16)),   # 2^30 elements through the fused plane kernel
     ((3, 715827883), (2, 7)),           # more than 2^31 elements (64-bit indexing)
-], ids=["2^30_plane", "over_2^31"])
+    ((1 << 25,), (8,)),                 # the most chunks the chunked 1-D kernels take (8192)
+    (((1 << 25) + 1,), (8,)),          # one element more: the generic 1-D path
+], ids=["2^30_plane", "over_2^31", "1d_8192_chunks", "1d_8193_chunks"])
 def test_max_size_closed_form(shape, box):
     """All-ones int32 tensors at the largest sizes: included sums have the
     closed form prod_i min(k_i, n_i - x_i) and excluded sums N - included
