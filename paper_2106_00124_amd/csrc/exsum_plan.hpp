@@ -22,6 +22,14 @@
 // stream (the plain call); the batched form records them into work lists.
 // Buffers come from an Arena over the caller's workspace; in "dry" mode the
 // arena only measures, so sizing and execution share one code path.
+//
+// Kernel choice (each special path applies only where the sink offers it and
+// its size rules hold; otherwise the generic one-axis passes run): a level of
+// rank >= 3 streams its first axis with the fused plane kernels; a rank-2
+// level with the fused row stream; the rank-3 level also hands the last two
+// levels to one workgroup when their table is small; the last (1-D) level
+// runs in one workgroup when short and in chunks when long; trailing axes
+// that fit in LDS are box-summed in one staged pass.
 #pragma once
 #include <algorithm>
 
@@ -126,7 +134,7 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
     const i64 N = prod(n, 0, d);
     // a level of rank >= 3 streams its first axis with the fused plane kernel
     // when it applies; it box-sums the two trailing axes itself, the middle
-    // axes are done first (levels below 0 only for strong excluded sums)
+    // axes are done first (levels past 0 exist only for strong excluded sums)
     bool fz[EXS_MAX_RANK] = {};
     for (int j = 0; j < (want_exc ? d : 1); ++j)
         fz[j] = sink.fused_ok && sizeof(T) == 4 &&
