@@ -666,16 +666,19 @@ def spot_check(a_host, w, outs, np, ops=None):
 
 def cpu_baseline(a_host, w, N):
     """The oracle (plain C, OpenMP, FP64) on the full step: included and
-    excluded sums for every op of the workload."""
+    excluded sums for every op of the workload; the median of three runs."""
     import oracle
     o = oracle.default()
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    t0 = time.perf_counter()
-    for op in w.ops:
-        o.scale(a_host, w.box, op, w.dtype)
-    dt = time.perf_counter() - t0
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        for op in w.ops:
+            o.scale(a_host, w.box, op, w.dtype)
+        times.append(time.perf_counter() - t0)
+    dt = sorted(times)[1]
     return {"value": round(N * len(w.ops) / dt / 1e9, 4), "unit": "Gelem/s", "cores": cores,
-            "kind": "oracle", "seconds": round(dt, 2),
+            "kind": "oracle", "seconds": round(dt, 2), "runs": 3,
             "sample": "full step: included+excluded sums, ops %s, on the whole %s tensor"
                       % ("+".join(w.ops), "x".join(map(str, w.shape))),
             "cpu": platform.processor() or platform.machine()}
