@@ -579,7 +579,9 @@ struct PlaneScanArgs {
     i64 tilesY, tilesX;
 };
 
-template <typename T, class Op, int KP, int QMAX>
+// FULL: exactly QMAX blocks and no middle axes (G == Ga), so every round is
+// full and known at compile time: the loads' wait counts are exact.
+template <typename T, class Op, int KP, int QMAX, bool FULL>
 __global__ void __launch_bounds__(1024) k_plane_scan(PlaneScanArgs a) {
     using C = PlaneCfg<KP>;
     constexpr int NT = C::NT, P = C::P, SA = C::SA, SB = C::SB;
@@ -598,12 +600,12 @@ __global__ void __launch_bounds__(1024) k_plane_scan(PlaneScanArgs a) {
     const int mid = (int)(wg / tiles);
     const int ky = a.ky, kx = a.kx;
     const int NY = (int)a.NY, NX = (int)a.NX;
-    const int Q = (int)a.Q;
+    const int Q = FULL ? QMAX : (int)a.Q;
     const int y0 = (int)(tile / a.tilesX) * (C::NBY * ky);
     const int x0 = (int)(tile % a.tilesX) * (C::NBX * kx);
     const i64 plane = (i64)NY * NX;
     const unsigned plane_bytes = (unsigned)(plane * (i64)sizeof(T));
-    const bool same = a.G == a.Ga;
+    const bool same = FULL || a.G == a.Ga;
 
     const int pyb = tid / C::TXM, pxb = tid % C::TXM;
     const int py = (pyb / KP) * ky + pyb % KP, px = (pxb / KP) * kx + pxb % KP;
@@ -761,8 +763,12 @@ void launch_plane_scan_kp(PlaneScanArgs pa, hipStream_t st) {
     pa.tilesY = (pa.NY + ty - 1) / ty;
     pa.tilesX = (pa.NX + tx - 1) / tx;
     const i64 grid = pa.tilesY * pa.tilesX * pa.MID;
-    hipLaunchKernelGGL((k_plane_scan<T, Op, KP, 32>), dim3((unsigned)grid), dim3(C::NT), 0, st,
-                       pa);
+    if (pa.Q == 32 && pa.G == pa.Ga)
+        hipLaunchKernelGGL((k_plane_scan<T, Op, KP, 32, true>), dim3((unsigned)grid), dim3(C::NT),
+                           0, st, pa);
+    else
+        hipLaunchKernelGGL((k_plane_scan<T, Op, KP, 32, false>), dim3((unsigned)grid),
+                           dim3(C::NT), 0, st, pa);
 }
 
 template <typename T, class Op>
