@@ -130,7 +130,21 @@ __global__ __launch_bounds__(1024) void k_tail_scan(const T* __restrict__ A1, T*
     const T e = Op::template id<T>();
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int QN = Q * n, pitch = n | 1;
-    for (int i = t; i < QN; i += TAIL_THREADS) tab[(i / n) * pitch + i % n] = A1[i];
+    {
+        // every load issued before the first LDS write
+        constexpr int TL = (TAIL_TABLE + TAIL_THREADS - 1) / TAIL_THREADS;
+        T g[TL];
+#pragma unroll
+        for (int r = 0; r < TL; ++r) {
+            const int i = t + r * TAIL_THREADS;
+            g[r] = i < QN ? A1[i] : e;
+        }
+#pragma unroll
+        for (int r = 0; r < TL; ++r) {
+            const int i = t + r * TAIL_THREADS;
+            if (i < QN) tab[(i / n) * pitch + i % n] = g[r];
+        }
+    }
     __syncthreads();
     for (int x = t; x < n; x += TAIL_THREADS) {
         T r = e;
