@@ -104,6 +104,7 @@ exs_status validate_job(const exs_job* job, bool check_ptrs) {
 struct TimingRec {
     std::string name;
     hipEvent_t a, b;
+    bool ended;  // the end event was recorded
 };
 static std::mutex g_tmu;
 static bool g_timing = false;
@@ -129,9 +130,14 @@ KTimer::KTimer(const char* name, hipStream_t stream) : slot(-1), st(stream) {
     if (!g_timing) return;
     std::string nm(name);
     if (g_tag >= 0) nm += "@L" + std::to_string(g_tag);
-    TimingRec r{nm, take_event(), take_event()};
-    if (!r.a || !r.b) return;
-    hipEventRecord(r.a, st);
+    TimingRec r{nm, take_event(), take_event(), false};
+    if (!r.a || !r.b || hipEventRecord(r.a, st) != hipSuccess) {
+        // timing is best-effort: a launch whose events cannot be recorded is
+        // left out of the totals
+        if (r.a) g_event_pool.push_back(r.a);
+        if (r.b) g_event_pool.push_back(r.b);
+        return;
+    }
     g_pending.push_back(r);
     slot = (int)g_pending.size() - 1;
 }
@@ -139,7 +145,8 @@ KTimer::KTimer(const char* name, hipStream_t stream) : slot(-1), st(stream) {
 KTimer::~KTimer() {
     if (slot < 0) return;
     std::lock_guard<std::mutex> g(g_tmu);
-    if (slot < (int)g_pending.size()) hipEventRecord(g_pending[slot].b, st);
+    if (slot < (int)g_pending.size())
+        g_pending[slot].ended = hipEventRecord(g_pending[slot].b, st) == hipSuccess;
 }
 
 // Launches every step at once on one stream (the plain call).
@@ -314,13 +321,14 @@ exs_status exs_timing_read(int32_t max, char* names, int64_t* launches, double* 
     std::map<std::string, std::pair<int64_t, double>> acc;
     std::vector<std::string> order;
     for (auto& r : g_pending) {
-        if (hipEventSynchronize(r.b) != hipSuccess)
+        if (r.ended && hipEventSynchronize(r.b) != hipSuccess)
             return set_error(EXS_EDEVICE, "hipEventSynchronize failed");
         float ms = 0.f;
-        hipEventElapsedTime(&ms, r.a, r.b);
-        if (!acc.count(r.name)) order.push_back(r.name);
-        acc[r.name].first += 1;
-        acc[r.name].second += ms;
+        if (r.ended && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            if (!acc.count(r.name)) order.push_back(r.name);
+            acc[r.name].first += 1;
+            acc[r.name].second += ms;
+        }
         g_event_pool.push_back(r.a);
         g_event_pool.push_back(r.b);
     }

@@ -439,9 +439,13 @@ static exs_status autotune(exs_batch* b, const char* path) {
         if (ws) (void)hipFree(ws);
         return set_error(EXS_EDEVICE, "hipStreamCreate failed");
     }
-    hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipStreamDestroy(st);
+        if (ws) (void)hipFree(ws);
+        return set_error(EXS_EDEVICE, "hipEventCreate failed");
+    }
     const i64 mts[] = {4096, 16384, 65536};
     const int wgs[] = {2, 4, 8};
     TuneCfg best = b->cfg;
@@ -455,15 +459,15 @@ static exs_status autotune(exs_batch* b, const char* path) {
             rc = build(b, ws, c);
             if (rc != EXS_OK) break;
             enqueue(b, c, st);  // warm-up
-            (void)hipEventRecord(e0, st);
+            bool ok = hipEventRecord(e0, st) == hipSuccess;
             for (int r = 0; r < 3; ++r) enqueue(b, c, st);
-            (void)hipEventRecord(e1, st);
-            if (hipEventSynchronize(e1) != hipSuccess) {
+            ok = ok && hipEventRecord(e1, st) == hipSuccess;
+            float ms = 0.f;
+            if (!ok || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
                 rc = set_error(EXS_EDEVICE, "autotuning run failed");
                 break;
             }
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
             ms /= 3.f;
             if (ms < best_ms) {
                 best_ms = ms;
