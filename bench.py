@@ -39,6 +39,9 @@ def parse():
     p.add_argument("--sweep-d", action="store_true",
                    help="instead of the headline step: excluded sums of fp32 tensors of about "
                         "2^24 elements for d = 1..8, box side 8 (strong and weak, +)")
+    p.add_argument("--sweep-n", action="store_true",
+                   help="instead of the headline step: excluded sums of fp32 cubes n^3 for "
+                        "n = 64..640, box 16^3, + (time per element against N)")
     p.add_argument("--no-weak", action="store_true",
                    help="skip the weak excluded sums (total - included) for +")
     p.add_argument("--no-batched", action="store_true", help="skip the batched form")
@@ -135,6 +138,9 @@ def main():
     import paper_2106_00124_amd as P
     if args.sweep_d:
         sweep_d(args, P, torch, np)
+        return
+    if args.sweep_n:
+        sweep_n(args, P, torch, np)
         return
     from paper_2106_00124_amd import _lib
     from paper_2106_00124_amd.workloads import WORKLOADS
@@ -404,6 +410,60 @@ def sweep_d(args, P, torch, np):
     print(json.dumps({"metric": "excluded-sum Gelem/s vs rank d (about 2^24 fp32 elements, "
                                 "box side 8, +)", "unit": "Gelem/s", "n_gpus": 1,
                       "data": "synthetic", "sweep": rows}), flush=True)
+
+
+def sweep_n(args, P, torch, np):
+    """Scaling in the size N at d = 3: fp32 (device counter fill) cubes n^3
+    for n from 64 to 640, box 16^3, included and excluded sums under + (the
+    paper reports a flat time per element in 3-D).  Each size is checked at
+    sampled cells against the oracle."""
+    import oracle
+    from tests import tolerance
+    from paper_2106_00124_amd import workloads as W
+    o = oracle.default()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for n in (64, 128, 192, 256, 384, 512, 640):
+        shape, box = (n, n, n), (16, 16, 16)
+        N = n ** 3
+        x = torch.empty(shape, dtype=torch.float32, device=dev)
+        P.fill(x, W.FILL_NORMALISH, 200 + n)
+        ws = torch.empty(max(P.workspace_size(shape, box, torch.float32, "sum", "both"), 1),
+                         dtype=torch.uint8, device=dev)
+        inc, exc = torch.empty_like(x), torch.empty_like(x)
+        for _ in range(2):
+            P.run(x, box, "sum", "both", inc_out=inc, exc_out=exc, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = max(3, args.steps)
+        e0.record(stream)
+        for _ in range(reps):
+            P.run(x, box, "sum", "both", inc_out=inc, exc_out=exc, workspace=ws, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res = {"n": n, "elements": N, "ms": round(ms, 4),
+               "ns_per_elem": round(ms * 1e6 / N, 4),
+               "gelem_per_s": round(N / (ms * 1e-3) / 1e9, 2)}
+        pts = np.random.default_rng(n).integers(0, N, 8)
+        host = W.counter_fill(W.FILL_NORMALISH, "f32", N, 200 + n).reshape(shape)
+        got = exc.reshape(-1)[torch.from_numpy(pts).to(dev)].cpu().numpy()
+        ref = o.point_exc(host, box, "sum", "f32", pts)
+        sig = tolerance.sigma_points(o, host, box, "exc", pts)
+        try:
+            tolerance.check(got, ref, "f32", "sum", sig)
+            res["check"] = "ok"
+        except AssertionError as err:
+            res["check"] = str(err)[:120]
+        log(f"n={n} {ms:.3f} ms {res['ns_per_elem']:.4f} ns/elem check {res['check']}")
+        rows.append(res)
+        del x, inc, exc, ws, host
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "excluded-sum Gelem/s vs N (fp32 cubes, box 16^3, +)",
+                      "unit": "Gelem/s", "n_gpus": 1, "data": "synthetic", "sweep": rows}),
+          flush=True)
 
 
 def _pct(v, p):
