@@ -84,6 +84,32 @@ def test_workspace_sizes_sane():
         assert st == 0
 
 
+def test_workspace_sizes_random_jobs():
+    """The planner's sizing pass (the same code path as the launches, with
+    nothing launched) over random valid jobs: every rank, dtype, operator and
+    mode, boxes from 1 to the full extent, shapes from tiny to 2^33 elements,
+    so that every special path (fused levels, tail scan, chunked 1-D levels,
+    staged trailing axes, segmented block scans) is planned somewhere."""
+    import numpy as np
+    rng = np.random.default_rng(2024)
+    planned = 0
+    for _ in range(3000):
+        d = int(rng.integers(1, 9))
+        shape = [int(v) + 1 for v in np.exp(rng.uniform(0, np.log(700), d)).astype(int)]
+        if np.prod(shape, dtype=np.float64) > 2.0 ** 33:
+            continue
+        box = [int(rng.integers(1, n + 1)) if rng.random() < 0.6 else min(n, int(rng.integers(1, 17)))
+               for n in shape]
+        dtype, op = int(rng.integers(0, 4)), int(rng.integers(0, 3))
+        mode = [1, 2, 3, 6, 7][int(rng.integers(0, 5))]
+        if mode & 4 and op != 0:
+            mode = 3
+        st, n = _ws(shape, box, dtype, op, mode)
+        assert st == 0, (shape, box, dtype, op, mode)
+        planned += 1
+    assert planned > 2000
+
+
 def test_run_rejects_null_and_aliasing_on_host():
     """Argument checks happen before anything touches the device."""
     from paper_2106_00124_amd import _lib
