@@ -64,13 +64,26 @@ struct PlaneCfg {
     static constexpr int CT = (P * TXM * NBY + NT - 1) / NT;   // column tasks per thread
 };
 
-// Blocks of axis 0 per workgroup run of the streaming kernel: enough runs
-// that the workgroups cover every CU (each run reads one extra block).
+// Blocks of axis 0 per workgroup run of the streaming kernel.  The stream
+// kernel fills a CU with one workgroup, so a launch of W workgroups takes
+// ceil(W / 256) waves, each as long as one run (its blocks plus the one
+// lookahead block every run reads): the split of the tiles' blocks into runs
+// that minimises waves x (blocks per run + 1) wins, the fewest runs on ties.
 inline i64 plane_run_blocks(i64 Q, i64 tiles) {
-    i64 nseg = (256 + tiles - 1) / tiles;
-    if (nseg > Q) nseg = Q;
-    if (nseg < 1) nseg = 1;
-    return (Q + nseg - 1) / nseg;
+    constexpr i64 CUS = 256;
+    i64 best = Q > 0 ? Q : 1, best_cost = -1;
+    const i64 maxseg = Q < 64 ? Q : 64;
+    for (i64 nseg = 1; nseg <= maxseg; ++nseg) {
+        const i64 sb = (Q + nseg - 1) / nseg;
+        const i64 runs = (Q + sb - 1) / sb;
+        const i64 waves = (tiles * runs + CUS - 1) / CUS;
+        const i64 cost = waves * (sb + 1);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = sb;
+        }
+    }
+    return best;
 }
 
 // Tiles of the (NY, NX) plane for boxes (ky, kx) (the KP bucket's tile shape).
