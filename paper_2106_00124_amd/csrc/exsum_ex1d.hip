@@ -24,7 +24,6 @@
 namespace exs {
 
 constexpr int L1_THREADS = 256;
-constexpr int L1_MAXE = 30;                      // k * ceil(16 / k) for k <= 16
 constexpr int L1_SCAN_THREADS = 1024, L1_SCAN_PER = 8;
 constexpr int L1_MAX_CHUNKS = L1_SCAN_THREADS * L1_SCAN_PER;
 
@@ -286,7 +285,7 @@ void launch_long1d(const T* A, T* exc, T* inc, i64 n, i64 k, T* Tt, T* Ut, T* CP
         EXS_L1_CASE(28)
         EXS_L1_CASE(30)
 #undef EXS_L1_CASE
-        default: break;
+        default: break;  // not reached: long1d_ok admits k <= 16, whose E are the cases above
     }
 }
 
