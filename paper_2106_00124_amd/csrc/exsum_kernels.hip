@@ -139,10 +139,20 @@ __global__ __launch_bounds__(1024) void k_tail_scan(const T* __restrict__ A1, T*
             const int i = t + r * TAIL_THREADS;
             g[r] = i < QN ? A1[i] : e;
         }
+        // (row, column) of element t + r * TAIL_THREADS, stepped without a
+        // division per element
+        const int dq = TAIL_THREADS / n, dc = TAIL_THREADS % n;
+        int qq = t / n, cc = t % n;
 #pragma unroll
         for (int r = 0; r < TL; ++r) {
             const int i = t + r * TAIL_THREADS;
-            if (i < QN) tab[(i / n) * pitch + i % n] = g[r];
+            if (i < QN) tab[qq * pitch + cc] = g[r];
+            qq += dq;
+            cc += dc;
+            if (cc >= n) {
+                cc -= n;
+                ++qq;
+            }
         }
     }
     __syncthreads();
