@@ -49,17 +49,20 @@ __global__ __launch_bounds__(TB_THREADS) void k_bdbs_tail(const T* __restrict__ 
             for (int r = t; r < rows; r += TB_THREADS) {
                 const int base = (r / st) * n * st + r % st;
                 // range suffix within each block (blocks end at multiples of
-                // k and at the row's end)
+                // k and at the row's end); off is x's offset in its block
                 T s = e;
+                int off = (n - 1) % k;
                 for (int x = n - 1; x >= 0; --x) {
                     const T v = a[base + x * st];
-                    s = ((x + 1) % k == 0 || x == n - 1) ? v : Op::apply(v, s);
+                    s = (off == k - 1 || x == n - 1) ? v : Op::apply(v, s);
                     b[base + x * st] = s;
+                    off = off == 0 ? k - 1 : off - 1;
                 }
                 // op the next block's range prefix up to x + k - 1
                 T q = e;
-                for (int x = 0; x < n; ++x) {
-                    if (x % k == 0) {
+                off = 0;
+                for (int x = 0; x < n; ++x, off = off + 1 == k ? 0 : off + 1) {
+                    if (off == 0) {
                         q = e;
                         continue;
                     }
