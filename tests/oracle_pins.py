@@ -21,6 +21,7 @@ itself):
 from __future__ import annotations
 
 import itertools
+import os
 
 import numpy as np
 from numpy.lib.stride_tricks import sliding_window_view
@@ -35,63 +36,60 @@ I64_MAX = np.iinfo(np.int64).max
 # hand-derived cases (from the Definition, Sec. 2)
 # --------------------------------------------------------------------------
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load_golden(name):
+    """A hand-derived fixture of tests/golden/: shape, box, the input A and the
+    expected included/excluded sums per operator (each file states its
+    derivation and citation)."""
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].split()
+            if not line:
+                continue
+            if line[0] in ("shape", "box"):
+                out[line[0]] = [int(v) for v in line[1:]]
+            elif line[0] == "A":
+                out["A"] = np.array([int(v) for v in line[1:]], np.int64)
+            else:
+                out[(line[0], line[1])] = np.array([int(v) for v in line[2:]], np.int64)
+    out["A"] = out["A"].reshape(out["shape"])
+    for key in list(out):
+        if isinstance(key, tuple):
+            out[key] = out[key].reshape(out["shape"])
+    return out
+
+
 def pin_hand_1d(o):
-    # A = 1..8, k = 4 (the shape of the 1-D example of Sec. 3, whose figure
-    # values are not available; derived here by hand from the definition).
-    a = np.arange(1, 9)
-    inc_sum = [1 + 2 + 3 + 4, 2 + 3 + 4 + 5, 3 + 4 + 5 + 6, 4 + 5 + 6 + 7, 5 + 6 + 7 + 8,
-               6 + 7 + 8, 7 + 8, 8]
-    exc_sum = [5 + 6 + 7 + 8, 1 + 6 + 7 + 8, 1 + 2 + 7 + 8, 1 + 2 + 3 + 8, 1 + 2 + 3 + 4,
-               1 + 2 + 3 + 4 + 5, 1 + 2 + 3 + 4 + 5 + 6, 1 + 2 + 3 + 4 + 5 + 6 + 7]
-    inc_max = [4, 5, 6, 7, 8, 8, 8, 8]
-    exc_max = [8, 8, 8, 8, 4, 5, 6, 7]
-    # min: the box at x starts with its smallest element; every complement but
-    # the first holds A[0] = 1
-    inc_min = [1, 2, 3, 4, 5, 6, 7, 8]
-    exc_min = [5, 1, 1, 1, 1, 1, 1, 1]
+    # A = 1..8, k = 4 (tests/golden/hand_1d_n8_k4.txt)
+    g = load_golden("hand_1d_n8_k4.txt")
+    a, k = g["A"], g["box"]
     for fn in ("brute", "scale"):
         for dt in ("i64", "i32", "f64", "f32"):
-            i, e = getattr(o, fn)(a, [4], "sum", dt)
-            assert np.array_equal(i, inc_sum) and np.array_equal(e, exc_sum), (fn, dt, i, e)
-            i, e = getattr(o, fn)(a, [4], "max", dt)
-            assert np.array_equal(i, inc_max) and np.array_equal(e, exc_max), (fn, dt, i, e)
-            i, e = getattr(o, fn)(a, [4], "min", dt)
-            assert np.array_equal(i, inc_min) and np.array_equal(e, exc_min), (fn, dt, i, e)
-    pts = np.arange(8)
-    assert np.array_equal(o.point_inc(a, [4], "sum", "i64", pts), inc_sum)
-    assert np.array_equal(o.point_exc(a, [4], "sum", "i64", pts), exc_sum)
-    assert np.array_equal(o.point_exc_direct(a, [4], "sum", "i64", pts), exc_sum)
-    assert np.array_equal(o.point_exc(a, [4], "max", "i64", pts), exc_max)
-    assert np.array_equal(o.point_inc(a, [4], "min", "i64", pts), inc_min)
-    assert np.array_equal(o.point_exc(a, [4], "min", "i64", pts), exc_min)
-    assert np.array_equal(o.point_exc_direct(a, [4], "min", "i64", pts), exc_min)
+            for op in ("sum", "max", "min"):
+                i, e = getattr(o, fn)(a, k, op, dt)
+                assert np.array_equal(i, g[("inc", op)]) and np.array_equal(e, g[("exc", op)]), \
+                    (fn, dt, op, i, e)
+    pts = np.arange(a.size)
+    for op in ("sum", "max", "min"):
+        assert np.array_equal(o.point_inc(a, k, op, "i64", pts), g[("inc", op)]), op
+        assert np.array_equal(o.point_exc(a, k, op, "i64", pts), g[("exc", op)]), op
+        assert np.array_equal(o.point_exc_direct(a, k, op, "i64", pts), g[("exc", op)]), op
 
 
 def pin_hand_2d(o):
-    # 3 x 4 matrix 1..12, box (2, 2); boxes clip at the high edges.
-    a = np.arange(1, 13).reshape(3, 4)
-    inc_sum = np.array([[1 + 2 + 5 + 6, 2 + 3 + 6 + 7, 3 + 4 + 7 + 8, 4 + 8],
-                        [5 + 6 + 9 + 10, 6 + 7 + 10 + 11, 7 + 8 + 11 + 12, 8 + 12],
-                        [9 + 10, 10 + 11, 11 + 12, 12]])
-    exc_sum = 78 - inc_sum  # 78 = 1 + ... + 12, and the box partitions the rest
-    inc_max = np.array([[6, 7, 8, 8], [10, 11, 12, 12], [10, 11, 12, 12]])
-    # 12 sits at (2, 3): only the boxes at (1,2), (1,3), (2,2), (2,3) hold it
-    exc_max = np.array([[12, 12, 12, 12], [12, 12, 10, 11], [12, 12, 10, 11]])
-    # min: each box starts at its smallest element; 1 sits at (0, 0), so only
-    # the box at (0, 0) holds it, and its complement's smallest is 3
-    inc_min = a.copy()
-    exc_min = np.array([[3, 1, 1, 1], [1, 1, 1, 1], [1, 1, 1, 1]])
+    # 3 x 4 matrix 1..12, box (2, 2) (tests/golden/hand_2d_3x4_k2x2.txt)
+    g = load_golden("hand_2d_3x4_k2x2.txt")
+    a, k = g["A"], g["box"]
     for dt in ("i64", "f64"):
-        for fn in ("brute", "scale"):
-            i, e = getattr(o, fn)(a, [2, 2], "sum", dt)
-            assert np.array_equal(i, inc_sum) and np.array_equal(e, exc_sum), (fn, dt)
-            i, e = getattr(o, fn)(a, [2, 2], "max", dt)
-            assert np.array_equal(i, inc_max) and np.array_equal(e, exc_max), (fn, dt)
-            i, e = getattr(o, fn)(a, [2, 2], "min", dt)
-            assert np.array_equal(i, inc_min) and np.array_equal(e, exc_min), (fn, dt)
-        assert np.array_equal(o.corners2d(a, [2, 2], "sum", dt), exc_sum)
-        assert np.array_equal(o.corners2d(a, [2, 2], "max", dt), exc_max)
-        assert np.array_equal(o.corners2d(a, [2, 2], "min", dt), exc_min)
+        for op in ("sum", "max", "min"):
+            for fn in ("brute", "scale"):
+                i, e = getattr(o, fn)(a, k, op, dt)
+                assert np.array_equal(i, g[("inc", op)]) and np.array_equal(e, g[("exc", op)]), \
+                    (fn, dt, op)
+            assert np.array_equal(o.corners2d(a, k, op, dt), g[("exc", op)]), (dt, op)
 
 
 # --------------------------------------------------------------------------
