@@ -34,8 +34,11 @@ def parse():
     p.add_argument("--workload", default="d3_512_f32")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-check", action="store_true")
-    p.add_argument("--copy-probe", action="store_true",
-                   help="also time a plain device copy of the input (bandwidth ceiling)")
+    p.add_argument("--no-copy-probe", action="store_true",
+                   help="skip the plain device copy of the input (bandwidth ceiling)")
+    p.add_argument("--no-configs", action="store_true",
+                   help="skip the other single-tensor workloads (64x64 int64, 32^5 fp32, "
+                        "128x128x64x64 int32)")
     p.add_argument("--sweep-d", action="store_true",
                    help="instead of the headline step: excluded sums of fp32 tensors of about "
                         "2^24 elements for d = 1..8, box side 8 (strong and weak, +)")
@@ -47,8 +50,14 @@ def parse():
     p.add_argument("--no-batched", action="store_true", help="skip the batched form")
     p.add_argument("--no-served", action="store_true", help="skip the serving form")
     p.add_argument("--batch-count", type=int, default=512)
-    p.add_argument("--serve-seconds", type=float, default=4.0,
+    p.add_argument("--batch-check-points", type=int, default=500,
+                   help="sampled cells per batched tensor checked against the oracle")
+    p.add_argument("--serve-seconds", type=float, default=60.0,
                    help="window of the 2000 req/s Poisson stream that is served")
+    p.add_argument("--serial-seconds", type=float, default=10.0,
+                   help="window of the same arrivals run through the serial plain path")
+    p.add_argument("--serve-check", type=int, default=48,
+                   help="served requests whose results are checked at sampled cells")
     p.add_argument("--serve-budget-gib", type=float, default=32.0)
     p.add_argument("--serve-inflight", type=int, default=8)
     return p.parse_args()
@@ -73,17 +82,27 @@ def read_timings(L):
     return out
 
 
-def algorithmic_bytes(kernel, N, es, k0, outputs):
-    """Bytes a launch of `kernel` must move at level 0 (per launch): read the
-    input once, write each output once, plus the per-block suffix table."""
+def algorithmic_bytes(kernel, N, es, outputs):
+    """Bytes a launch of `kernel` must move at level 0: read the input once
+    and write each output once (the read-A-once / write-outputs-once minimum
+    of one pass)."""
     base = kernel.split("@")[0]
     if base in ("k_axis0", "k_plane_axis0"):
-        return N * es * (1 + outputs) + (N // k0) * es
+        return N * es * (1 + outputs)
     if base in ("k_bdbs", "k_plane_bdbs"):
         return 2 * N * es
-    if base == "k_blockagg":
-        return N * es + (N // k0) * es
+    if base in ("k_blockagg", "k_blockagg4"):
+        return N * es
     return None
+
+
+def overhead_bytes(kernel, N, es, k0):
+    """Reads a launch makes beyond its algorithmic bytes by design: the stream
+    kernel reads the block-suffix plane (one element per point and block)."""
+    base = kernel.split("@")[0]
+    if base in ("k_axis0", "k_plane_axis0"):
+        return (N // k0) * es
+    return 0
 
 
 TRAFFIC_SOURCES = ("exsum_plane.hpp", "exsum_device.hpp")
@@ -100,10 +119,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def profiled_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, calibrated by a plain copy), or None
-    when there is none or the kernel source changed since it was taken."""
+def profile_summary(kernel, workload):
+    """The committed rocprofv3 summary of `kernel` on `workload`: its traced
+    average launch duration and its HBM bytes per launch (FETCH_SIZE and
+    WRITE_SIZE, calibrated by a plain copy), or None when there is none or the
+    kernel source changed since it was taken."""
     path = os.path.join(HERE, "profiles", f"{kernel}_{workload}.md")
     if not os.path.exists(path):
         return None
@@ -117,10 +137,25 @@ def profiled_traffic(kernel, workload):
     try:
         if vals.get("kernel_source_sha256") != kernel_source_hash():
             return None
-        return {"fetch": int(vals["fetch_bytes_per_launch"]),
-                "write": int(vals["write_bytes_per_launch"])}
+        out = {"file": os.path.relpath(path, HERE),
+               "trace_avg_launch_us": float(vals["trace_avg_launch_us"])}
+        if "fetch_bytes_per_launch" in vals:
+            out["fetch"] = int(vals["fetch_bytes_per_launch"])
+            out["write"] = int(vals["write_bytes_per_launch"])
+        return out
     except (KeyError, ValueError):
         return None
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
 
 def main():
@@ -270,27 +305,41 @@ def main():
     excl_elems_per_step = N * len(w.ops)
     value = excl_elems_per_step / (ms_per_step * 1e-3) / 1e9
 
-    # dominant kernel roofline
+    # dominant kernel roofline: algorithmic bytes (read the input once, write
+    # both outputs once) over the kernel's average launch, timed by HIP events
+    # on its launch stream in the instrumented pass; the committed rocprofv3
+    # summary of the same kernel gives the traced average and the HBM bytes
     k0 = w.box[0]
     dom_name, (dom_launches, dom_total) = max(kt.items(), key=lambda kv: kv[1][1])
     dom_avg_s = dom_total / dom_launches * 1e-3
-    abytes = algorithmic_bytes(dom_name, N, es, k0, outputs=2) if dom_name.endswith("@L0") else None
+    abytes = algorithmic_bytes(dom_name, N, es, outputs=2) if dom_name.endswith("@L0") else None
     roofline = None
     if abytes is not None:
         achieved = abytes / dom_avg_s / 1e9
         kname = dom_name.split("@")[0]
-        tr = profiled_traffic(kname, w.name)
+        prof = profile_summary(kname, w.name)
+        tr = prof if prof and "fetch" in prof else None
         roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": (tr["fetch"] + tr["write"]) if tr else None,
-                    "traffic_split": tr, "avg_launch_us": round(dom_avg_s * 1e6, 1),
-                    "algorithmic_bytes_per_launch": int(abytes)}
+                    "traffic_split": {"fetch": tr["fetch"], "write": tr["write"]} if tr else None,
+                    "avg_launch_us": round(dom_avg_s * 1e6, 1),
+                    "launches": dom_launches,
+                    "algorithmic_bytes_per_launch": int(abytes),
+                    "algorithmic_rule": "12 B/elem: read the input once, write the included "
+                                        "and excluded sums once",
+                    "overhead_read_bytes_per_launch": int(overhead_bytes(kname, N, es, k0)),
+                    "profile": prof["file"] if prof else None,
+                    "profile_avg_launch_us": prof["trace_avg_launch_us"] if prof else None,
+                    "profile_frac": round(abytes / (prof["trace_avg_launch_us"] * 1e-6) / 1e9
+                                          / HBM_PEAK_GBS, 4) if prof else None}
     # whole-path figure: read A twice, write both outputs, per op
     path_bytes = len(w.ops) * N * es * (2 + 2)
     path_gbs = path_bytes / (ms_per_step * 1e-3) / 1e9
 
     copy = None
-    if args.copy_probe:
+    if not args.no_copy_probe:
+        # plain device copies of the input: the achievable read+write ceiling
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
@@ -303,7 +352,10 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         cms = e0.elapsed_time(e1) / 10
-        copy = {"ms": round(cms, 4), "GBps": round(2 * N * es / (cms * 1e-3) / 1e9, 1)}
+        cgbs = 2 * N * es / (cms * 1e-3) / 1e9
+        copy = {"ms": round(cms, 4), "GBps": round(cgbs, 1),
+                "frac_of_peak": round(cgbs / HBM_PEAK_GBS, 4),
+                "what": "torch copy_ of the %d MiB input (read + write)" % (N * es >> 20)}
         del b
 
     # parity spot check of the timed outputs against the oracle (sampled)
@@ -317,6 +369,7 @@ def main():
 
     del outs, ws
     torch.cuda.empty_cache()
+    configs = None if args.no_configs else bench_configs(args, P, torch, np)
     batched = None if args.no_batched else bench_batched(args, P, _lib, torch, np)
     served = None if args.no_served else bench_served(args, P, _lib, torch, np)
 
@@ -346,6 +399,7 @@ def main():
         "check": check,
         "weak": weak,
         "min": mn,
+        "configs": configs,
         "batched": batched,
         "served": served,
     }
@@ -466,6 +520,58 @@ def sweep_n(args, P, torch, np):
           flush=True)
 
 
+def bench_configs(args, P, torch, np):
+    """The other single-tensor workloads: 64x64 int64 (+, launch-bound:
+    microseconds per call), 32^5 fp32 and 128x128x64x64 int32 (+ and max),
+    both outputs; each timed per operator (median of the event-timed calls)
+    and checked at sampled cells against the oracle."""
+    from paper_2106_00124_amd.workloads import WORKLOADS
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name in ("d2_64x64_i64", "d5_32_f32", "d4_128x128x64x64_i32"):
+        w = WORKLOADS[name]
+        dt = {"f32": torch.float32, "i32": torch.int32, "i64": torch.int64}[w.dtype]
+        a_host = w.tensor()
+        a = torch.from_numpy(a_host).to(dev)
+        es = a.element_size()
+        ws = torch.empty(max(max(P.workspace_size(w.shape, w.box, dt, op, "both")
+                                 for op in w.ops), 1), dtype=torch.uint8, device=dev)
+        outs = {op: (torch.empty_like(a), torch.empty_like(a)) for op in w.ops}
+        r = {"shape": list(w.shape), "box": list(w.box), "dtype": w.dtype,
+             "outputs": ["included", "excluded"], "per_op": {}}
+        for op in w.ops:
+            inc, exc = outs[op]
+            for _ in range(3):
+                P.run(a, w.box, op, "both", inc_out=inc, exc_out=exc, workspace=ws, stream=stream)
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(max(20, args.steps)):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                P.run(a, w.box, op, "both", inc_out=inc, exc_out=exc, workspace=ws, stream=stream)
+                e1.record(stream)
+                times.append((e0, e1))
+            torch.cuda.synchronize()
+            ms = _pct([x.elapsed_time(y) for x, y in times], 0.5)
+            gbs = w.n * es * 4 / (ms * 1e-3) / 1e9
+            r["per_op"][op] = {"ms": round(ms, 4), "us": round(ms * 1e3, 1),
+                               "gelem_per_s": round(w.n / (ms * 1e-3) / 1e9, 2),
+                               "path_GBps": round(gbs, 1),
+                               "path_frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+        if not args.no_check:
+            r["check"] = spot_check(a_host, w, outs, np)
+        r["path_bytes_rule"] = "16 B/elem per op for 4-byte types (read the input twice, " \
+                               "write both outputs), 32 for 8-byte"
+        log(f"config {name}: " + ", ".join(f"{op} {v['ms']:.4f} ms ({v['gelem_per_s']} Gelem/s)"
+                                           for op, v in r["per_op"].items()))
+        res[name] = r
+        del a, ws, outs
+        torch.cuda.empty_cache()
+    return res
+
+
 def _pct(v, p):
     import math
     v = sorted(v)
@@ -483,15 +589,11 @@ def bench_batched(args, P, _lib, torch, np):
     dev = torch.device("cuda:0")
     L = _lib.lib()
     stream = torch.cuda.current_stream()
-    xs = []
-    for it in items:
-        x = torch.empty(it.shape, dtype=torch.float32 if it.dtype == "f32" else torch.int32,
-                        device=dev)
-        if it.dtype == "f32":
-            P.fill(x, W.FILL_NORMALISH, it.seed)
-        else:
-            P.fill(x, W.FILL_UNIFORM_INT, it.seed, -100, 100)
-        xs.append(x)
+    t0 = time.perf_counter()
+    hosts = [it.tensor() for it in items]   # f32 N(0,1), i32 uniform [-100, 100]
+    xs = [torch.from_numpy(h).to(dev) for h in hosts]
+    torch.cuda.synchronize()
+    log(f"batched: inputs generated and uploaded in {time.perf_counter() - t0:.1f}s")
     total = sum(it.n for it in items)
     log(f"batched: {len(items)} tensors, {total / 1e6:.1f} M elements")
     cache = os.environ.get("EXSUM_TUNE_CACHE",
@@ -545,17 +647,16 @@ def bench_batched(args, P, _lib, torch, np):
     per_tensor()
     torch.cuda.synchronize()
     pt = timed(per_tensor, max(3, reps // 2))
-    # agreement between the graph launch and the plain calls
-    exact = close = 0
-    worst = 0.0
+    # the graph launch's results against the oracle at sampled cells of every
+    # tensor (bit-exact for i32 and max, the per-cell f32 rule for +), and
+    # against the plain calls (bit-exact where the result is unique)
+    check = None
+    if not args.no_check:
+        check = check_batched(items, hosts, graph_out, np, args.batch_check_points)
+    exact = 0
     for (gi, ge), (pi, pe), it in zip(graph_out, outs, items):
-        for a, b in ((gi, pi), (ge, pe)):
-            if it.dtype == "i32" or it.op != "sum":
-                exact += int(torch.equal(a, b))
-            else:
-                d = ((a - b).abs().max() / b.abs().max().clamp_min(1e-30)).item()
-                worst = max(worst, d)
-                close += int(d <= 1e-5)
+        if it.dtype == "i32" or it.op != "sum":
+            exact += int(torch.equal(gi, pi)) + int(torch.equal(ge, pe))
     n_exact = sum(2 for it in items if it.dtype == "i32" or it.op != "sum")
     ms_g = _pct(g, 0.5)
     res = {
@@ -564,15 +665,14 @@ def bench_batched(args, P, _lib, torch, np):
         "eager_ms_p50": round(_pct(e, 0.5), 4),
         "per_tensor_ms_p50": round(_pct(pt, 0.5), 4),
         "gelem_per_s": round(total / (ms_g * 1e-3) / 1e9, 2),
+        "GBps_at_16B_per_elem": round(total * 16 / (ms_g * 1e-3) / 1e9, 1),
         "per_tensor_gelem_per_s": round(total / (_pct(pt, 0.5) * 1e-3) / 1e9, 2),
         "speedup_vs_per_tensor": round(_pct(pt, 0.5) / ms_g, 3),
         "graph_nodes": info["graph_nodes"], "work_items": info["work_items"],
         "build_s": round(build_s, 2),
-        "agree_with_plain": {"bit_exact": f"{exact}/{n_exact}",
-                             "f32_sum_within_1e-5": f"{close}/{2 * len(items) - n_exact}",
-                             "f32_sum_worst_rel": worst},
-        "values": "device counter fill: f32 normalish (sum of four uniforms), i32 uniform "
-                  "[-100,100]",
+        "check": check,
+        "plain_call_bit_exact": f"{exact}/{n_exact} (integer and max outputs)",
+        "values": "host numpy PCG64: f32 N(0,1), i32 uniform [-100,100], one seed per tensor",
     }
     log(f"batched: graph {ms_g:.3f} ms, eager {res['eager_ms_p50']:.3f} ms, "
         f"per-tensor {res['per_tensor_ms_p50']:.3f} ms")
@@ -581,9 +681,12 @@ def bench_batched(args, P, _lib, torch, np):
 
 
 def bench_served(args, P, _lib, torch, np):
-    """Serving form: a window of the Poisson request stream (excluded sums,
-    inputs generated on the device) through the server, vs the serial plain
-    path (one request at a time on one stream) on the same arrivals."""
+    """Serving form: the Poisson request stream (excluded sums, inputs
+    generated on the device) through the server, vs the serial plain path (one
+    request at a time on one stream) on the first seconds of the same
+    arrivals.  A sample of the served results (the largest requests, the
+    longest boxes, and uniform draws) is checked at sampled cells against the
+    oracle on the inputs regenerated on the host."""
     from paper_2106_00124_amd import workloads as W
     reqs = W.serving_workload(duration_s=args.serve_seconds)
     elems = sum(r.n for r in reqs)
@@ -598,26 +701,47 @@ def bench_served(args, P, _lib, torch, np):
     S.drain()
     S.close()
 
+    # requests whose results are checked: the largest, the longest boxes, and
+    # uniform draws from the rest
+    rng = np.random.default_rng(606)
+    want = sorted(range(len(reqs)), key=lambda i: -reqs[i].n)[:4]
+    want += sorted(range(len(reqs)), key=lambda i: -max(reqs[i].box))[:4]
+    want += [int(i) for i in rng.choice(len(reqs), size=max(0, args.serve_check - 8),
+                                        replace=False)]
+    want = set(want) if args.serve_check > 0 and not args.no_check else set()
+    sampled = {}
+
     def open_loop(S):
         from collections import deque
         pend = deque()
         late = []
         t0 = time.perf_counter()
-        for r in reqs:
+
+        def retire_head():
+            t, i = pend.popleft()
+            if i in want:
+                r = reqs[i]
+                _, exc, _ = S.result(t)
+                pts = np.concatenate([rng.integers(0, r.n, 30), [0, r.n - 1]]).astype(np.int64)
+                sampled[i] = (pts, exc.reshape(-1)[torch.from_numpy(pts).to(exc.device)]
+                              .cpu().numpy())
+            S.release(t)
+
+        for i, r in enumerate(reqs):
             while True:
                 now = time.perf_counter() - t0
-                while pend and S.done(pend[0]):
-                    S.release(pend.popleft())
+                while pend and S.done(pend[0][0]):
+                    retire_head()
                 if now >= r.arrival_s:
                     break
                 if r.arrival_s - now > 3e-4:
                     time.sleep(1e-4)
             late.append(time.perf_counter() - t0 - r.arrival_s)
-            pend.append(S.submit_generated(r.shape, r.box, torch.float32, r.op, "exc",
-                                           kind=W.FILL_LOGMAG, seed=r.fill_seed))
+            pend.append((S.submit_generated(r.shape, r.box, torch.float32, r.op, "exc",
+                                            kind=W.FILL_LOGMAG, seed=r.fill_seed), i))
         while pend:
-            if S.done(pend[0]):
-                S.release(pend.popleft())
+            if S.done(pend[0][0]):
+                retire_head()
         wall = time.perf_counter() - t0
         return late, wall
 
@@ -626,7 +750,8 @@ def bench_served(args, P, _lib, torch, np):
     late, wall = open_loop(S)
     st = S.stats()
     S.close()
-    log(f"served: p50 {st['p50_ms']:.3f} ms p99 {st['p99_ms']:.3f} ms, {st['req_per_s']:.0f} req/s")
+    log(f"served: p50 {st['p50_ms']:.3f} ms p99 {st['p99_ms']:.3f} ms, {st['req_per_s']:.0f} req/s "
+        f"over {wall:.1f}s")
 
     # saturated: every request submitted at once (throughput)
     S = P.Server(hbm_budget=int(args.serve_budget_gib * (1 << 30)),
@@ -644,14 +769,17 @@ def bench_served(args, P, _lib, torch, np):
             S.release(pend.popleft())
     sat_s = time.perf_counter() - t0
     S.close()
+    log(f"served saturated: {len(reqs) / sat_s:.0f} req/s")
 
-    # serial plain path on one stream, same arrivals
+    # serial plain path on one stream, the first seconds of the same arrivals
+    sreqs = [r for r in reqs if r.arrival_s < args.serial_seconds]
+    selems = sum(r.n for r in sreqs)
     L = _lib.lib()
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
-    maxn = max(r.n for r in reqs)
+    maxn = max(r.n for r in sreqs)
     wsz = 0
-    for r in reqs:
+    for r in sreqs:
         wsz = max(wsz, P.workspace_size(r.shape, r.box, torch.float32, r.op, "exc"))
     xin = torch.empty(maxn, dtype=torch.float32, device=dev)
     xout = torch.empty(maxn, dtype=torch.float32, device=dev)
@@ -668,35 +796,109 @@ def bench_served(args, P, _lib, torch, np):
 
     lat = []
     t0 = time.perf_counter()
-    for r in reqs:
+    for r in sreqs:
         while time.perf_counter() - t0 < r.arrival_s:
             pass
         serial_one(r)
         stream.synchronize()
         lat.append((time.perf_counter() - t0 - r.arrival_s) * 1e3)
     t1 = time.perf_counter()
-    for r in reqs:
+    for r in sreqs:
         serial_one(r)
     stream.synchronize()
     serial_sat = time.perf_counter() - t1
+    del xin, xout, ws
+    check = check_served(reqs, sampled, np) if sampled else None
     res = {
         "requests": len(reqs), "window_s": args.serve_seconds, "rate_per_s": 2000,
+        "wall_s": round(wall, 2),
         "elements": int(elems), "outputs": ["excluded"], "hbm_budget_gib": args.serve_budget_gib,
         "max_inflight": args.serve_inflight,
         "p50_ms": round(st["p50_ms"], 4), "p99_ms": round(st["p99_ms"], 4),
+        "completed": st["completed"],
         "req_per_s": round(st["req_per_s"], 1), "gelem_per_s": round(st["gelem_per_s"], 3),
         "max_queue": st["max_queue"], "peak_bytes": st["peak_bytes"],
         "submit_lateness_p99_ms": round(_pct(late, 0.99) * 1e3, 4),
         "saturated_req_per_s": round(len(reqs) / sat_s, 1),
         "saturated_gelem_per_s": round(elems / sat_s / 1e9, 3),
+        "serial_window_s": args.serial_seconds, "serial_requests": len(sreqs),
         "serial_p50_ms": round(_pct(lat, 0.5), 4), "serial_p99_ms": round(_pct(lat, 0.99), 4),
-        "serial_saturated_req_per_s": round(len(reqs) / serial_sat, 1),
-        "serial_saturated_gelem_per_s": round(elems / serial_sat / 1e9, 3),
+        "serial_saturated_req_per_s": round(len(sreqs) / serial_sat, 1),
+        "serial_saturated_gelem_per_s": round(selems / serial_sat / 1e9, 3),
         "latency": "submit to completion seen by the server (serial: arrival to stream sync)",
+        "check": check,
     }
     log(f"serial: p50 {res['serial_p50_ms']:.3f} ms p99 {res['serial_p99_ms']:.3f} ms; "
         f"saturated {res['saturated_req_per_s']:.0f} vs {res['serial_saturated_req_per_s']:.0f} req/s")
     return res
+
+
+def check_served(reqs, sampled, np):
+    """Sampled cells of the checked served requests against the oracle on the
+    inputs regenerated on the host from each request's seed."""
+    import concurrent.futures as cf
+    import oracle
+    from paper_2106_00124_amd import workloads as W
+    from tests import tolerance
+    o = oracle.default()
+    t0 = time.perf_counter()
+
+    def one(i):
+        r = reqs[i]
+        pts, got = sampled[i]
+        host = W.counter_fill(W.FILL_LOGMAG, "f32", r.n, r.fill_seed).reshape(r.shape)
+        ref = o.point_exc(host, r.box, r.op, "f32", pts)
+        sig = tolerance.sigma_points(o, host, r.box, "exc", pts) if r.op == "sum" else None
+        try:
+            st = tolerance.check(got, ref, "f32", r.op, sig, what=f"request {r.rid}")
+            return None, st.get("max_scaled_err", 0.0)
+        except AssertionError as e:
+            return str(e)[:160], 0.0
+
+    with cf.ThreadPoolExecutor(8) as ex:
+        out = list(ex.map(one, sorted(sampled)))
+    bad = [e for e, _ in out if e]
+    return {"ok": not bad, "requests": len(sampled),
+            "largest_elements": max(reqs[i].n for i in sampled),
+            "longest_box_side": max(max(reqs[i].box) for i in sampled),
+            "cells_per_request": len(next(iter(sampled.values()))[0]),
+            "f32_sum_max_scaled_err": max(v for _, v in out), "failures": bad[:5],
+            "host_s": round(time.perf_counter() - t0, 1)}
+
+
+def check_batched(items, hosts, outs, np, npts):
+    """Every tensor of the batch at `npts` sampled cells (and its first and
+    last cell) against the oracle."""
+    import oracle
+    from tests import tolerance
+    o = oracle.default()
+    rng = np.random.default_rng(515)
+    t0 = time.perf_counter()
+    worst = 0.0
+    bad = []
+    cells = 0
+    for t, (it, a, (inc, exc)) in enumerate(zip(items, hosts, outs)):
+        pts = np.concatenate([rng.integers(0, it.n, npts), [0, it.n - 1]]).astype(np.int64)
+        idx = __import__("torch").from_numpy(pts).to(inc.device)
+        gi = inc.reshape(-1)[idx].cpu().numpy()
+        ge = exc.reshape(-1)[idx].cpu().numpy()
+        ri = o.point_inc(a, it.box, it.op, it.dtype, pts)
+        re_ = o.point_exc(a, it.box, it.op, it.dtype, pts)
+        si = se = None
+        if it.dtype == "f32" and it.op == "sum":
+            si = tolerance.sigma_points(o, a, it.box, "inc", pts)
+            se = tolerance.sigma_points(o, a, it.box, "exc", pts)
+        try:
+            s1 = tolerance.check(gi, ri, it.dtype, it.op, si, what=f"tensor {t} inc")
+            s2 = tolerance.check(ge, re_, it.dtype, it.op, se, what=f"tensor {t} exc")
+            worst = max(worst, s1.get("max_scaled_err", 0.0), s2.get("max_scaled_err", 0.0))
+        except AssertionError as e:
+            bad.append(str(e)[:160])
+        cells += 2 * len(pts)
+    return {"ok": not bad, "tensors": len(items), "cells_per_tensor": npts + 2,
+            "cells_checked": cells, "f32_sum_max_scaled_err": worst, "failures": bad[:5],
+            "rule": "bit-exact for i32 and max; f32 + |got-ref| <= 1e-5 max(|ref|, sigma)",
+            "host_s": round(time.perf_counter() - t0, 1)}
 
 
 def spot_check(a_host, w, outs, np, ops=None):
@@ -729,7 +931,6 @@ def cpu_baseline(a_host, w, N):
     excluded sums for every op of the workload; the median of three runs."""
     import oracle
     o = oracle.default()
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     times = []
     for _ in range(3):
         t0 = time.perf_counter()
@@ -737,11 +938,11 @@ def cpu_baseline(a_host, w, N):
             o.scale(a_host, w.box, op, w.dtype)
         times.append(time.perf_counter() - t0)
     dt = sorted(times)[1]
-    return {"value": round(N * len(w.ops) / dt / 1e9, 4), "unit": "Gelem/s", "cores": cores,
-            "kind": "oracle", "seconds": round(dt, 2), "runs": 3,
-            "sample": "full step: included+excluded sums, ops %s, on the whole %s tensor"
-                      % ("+".join(w.ops), "x".join(map(str, w.shape))),
-            "cpu": platform.processor() or platform.machine()}
+    return {"value": round(N * len(w.ops) / dt / 1e9, 4), "unit": "Gelem/s",
+            "cores": o.num_threads(), "kind": "oracle", "seconds": round(dt, 2), "runs": 3,
+            "sample": "full step: included+excluded sums, ops %s, on the whole %s tensor "
+                      "(median of 3 runs)" % ("+".join(w.ops), "x".join(map(str, w.shape))),
+            "cpu": cpu_model(), "host_logical_cpus": os.cpu_count()}
 
 
 if __name__ == "__main__":

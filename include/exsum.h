@@ -188,11 +188,15 @@ exs_status exs_server_create(size_t hbm_budget, int32_t max_inflight, exs_server
 /* Queue a request.  job->in_dev (caller-owned) must stay valid and
  * unchanged until the ticket completes; job->mode selects outputs; output
  * pointers in the job are ignored (the server allocates them in its arena).
- * Never blocks; fails only for an invalid job (EXS_EINVAL) or one larger
- * than the whole budget (EXS_ENOMEM).  A request that does not fit the free
- * arena waits in the queue, and so do the requests behind it.  The work
- * computes what exs_run computes for the same job. */
-exs_status exs_server_submit(exs_server *s, const exs_job *job, uint64_t *ticket);
+ * `stream` (a hipStream_t, NULL = the null stream) is the stream on which the
+ * caller wrote job->in_dev: an event is recorded on it here and the request's
+ * work waits for that event, so the input may still be in production when
+ * submit is called.  Never blocks; fails only for an invalid job (EXS_EINVAL),
+ * one larger than the whole budget (EXS_ENOMEM) or a failed event record
+ * (EXS_EDEVICE).  A request that does not fit the free arena waits in the
+ * queue, and so do the requests behind it.  The work computes what exs_run
+ * computes for the same job. */
+exs_status exs_server_submit(exs_server *s, const exs_job *job, void *stream, uint64_t *ticket);
 /* The same, but the server builds the input tensor itself inside its arena
  * (exs_fill with fill_kind/seed/lo/hi, enqueued on the request's stream just
  * before its work), so request tensors are produced and kept on the device.
@@ -213,9 +217,13 @@ exs_status exs_server_input(exs_server *s, uint64_t ticket, const void **in_dev)
  * request runs and the queue head cannot fit because completed requests
  * still hold the arena (release them, then drain again). */
 exs_status exs_server_drain(exs_server *s);
-/* Return a completed (or failed) request's memory to the arena and forget
- * its ticket; EXS_ENOTREADY while it is queued or running. */
-exs_status exs_server_release(exs_server *s, uint64_t ticket);
+/* Forget a completed (or failed) request's ticket and return its memory to
+ * the arena once `stream` (a hipStream_t, NULL = the null stream) has reached
+ * this call: work the caller enqueued there that reads the outputs (a copy,
+ * say) finishes before another request can reuse the range.  An event is
+ * recorded on `stream`; the range is free again when it completes.
+ * EXS_ENOTREADY while the request is queued or running. */
+exs_status exs_server_release(exs_server *s, uint64_t ticket, void *stream);
 /* Latency percentiles (submit -> completion event) and throughput over the
  * completed requests so far; queue depth and peak in-flight bytes. */
 exs_status exs_server_stats(exs_server *s, double *p50_ms, double *p99_ms,

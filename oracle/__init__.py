@@ -84,6 +84,8 @@ def _bind(lib):
     lib.orc_total_f64.restype = ctypes.c_double
     lib.orc_total_i64.argtypes = [L, I, I, P]
     lib.orc_total_i64.restype = ctypes.c_int64
+    lib.orc_num_threads.argtypes = []
+    lib.orc_num_threads.restype = ctypes.c_int
     return lib
 
 
@@ -236,6 +238,10 @@ class Oracle:
         if dtype == "i32":
             out = out.astype(np.int32).astype(np.int64)
         return out
+
+    def num_threads(self) -> int:
+        """OpenMP threads the oracle's parallel loops use."""
+        return int(self.lib.orc_num_threads())
 
     def total(self, a, op, dtype):
         a = np.asarray(a)

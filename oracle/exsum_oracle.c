@@ -59,6 +59,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#include <omp.h>
 
 #ifndef ORC_MUTANT
 #define ORC_MUTANT 0
@@ -543,6 +544,9 @@ int orc_point_exc_cover_i64(int d, const int64_t *n, const int64_t *k, int op, i
     i_cover_free(&c);
     return 0;
 }
+
+/* Threads the parallel loops above use (for reporting the oracle's timing). */
+int orc_num_threads(void) { return omp_get_max_threads(); }
 
 /* Reduction of the whole tensor (the identity for an empty tensor cannot
  * occur: N >= 1). */

@@ -195,7 +195,8 @@ class Server:
 
     ``submit`` returns a ticket; ``result`` returns ``(inc, exc)`` as torch
     views of the server's arena once the request completed (None before).
-    The views are valid until ``release``; clone them to keep them longer.
+    The views are valid until ``release``; clone them to keep them longer
+    (a clone enqueued on the stream passed to ``release`` is safe).
     """
 
     def __init__(self, hbm_budget, max_inflight=4):
@@ -206,12 +207,16 @@ class Server:
         self._meta = {}
         self._keep = {}
 
-    def submit(self, x, box, op="sum", mode="both"):
+    def submit(self, x, box, op="sum", mode="both", stream=None):
+        """Queue a request on input ``x``; its work waits for what ``stream``
+        (default: torch's current stream) has enqueued so far, so ``x`` may
+        still be in production there."""
         if not x.is_cuda or not x.is_contiguous():
             raise ExsError(1, "server inputs must be contiguous device tensors")
         j = job_for(x, box, op, mode)
         t = ctypes.c_uint64()
-        _lib.check(_lib.lib().exs_server_submit(self._h, ctypes.byref(j), ctypes.byref(t)))
+        _lib.check(_lib.lib().exs_server_submit(self._h, ctypes.byref(j), _stream_ptr(stream),
+                                                ctypes.byref(t)))
         self._meta[t.value] = (tuple(x.shape), j.dtype)
         self._keep[t.value] = x
         return t.value
@@ -266,8 +271,12 @@ class Server:
     def drain(self):
         _lib.check(_lib.lib().exs_server_drain(self._h))
 
-    def release(self, ticket):
-        _lib.check(_lib.lib().exs_server_release(self._h, ctypes.c_uint64(ticket)))
+    def release(self, ticket, stream=None):
+        """Forget ``ticket``; its memory is reused only after ``stream``
+        (default: torch's current stream) has finished what it has enqueued so
+        far, such as a copy of the result views."""
+        _lib.check(_lib.lib().exs_server_release(self._h, ctypes.c_uint64(ticket),
+                                                 _stream_ptr(stream)))
         self._meta.pop(ticket, None)
         self._keep.pop(ticket, None)
 

@@ -67,7 +67,7 @@ SIGNATURES = {
                                       ctypes.POINTER(ctypes.c_int64)]),
     "exs_batch_destroy": (None, [_P]),
     "exs_server_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(_P)]),
-    "exs_server_submit": (ctypes.c_int, [_P, _JP, ctypes.POINTER(ctypes.c_uint64)]),
+    "exs_server_submit": (ctypes.c_int, [_P, _JP, _P, ctypes.POINTER(ctypes.c_uint64)]),
     "exs_server_submit_generated": (ctypes.c_int, [_P, _JP, ctypes.c_int32, ctypes.c_uint64,
                                                    ctypes.c_int64, ctypes.c_int64,
                                                    ctypes.POINTER(ctypes.c_uint64)]),
@@ -75,7 +75,7 @@ SIGNATURES = {
     "exs_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(_P),
                                        ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_double)]),
     "exs_server_drain": (ctypes.c_int, [_P]),
-    "exs_server_release": (ctypes.c_int, [_P, ctypes.c_uint64]),
+    "exs_server_release": (ctypes.c_int, [_P, ctypes.c_uint64, _P]),
     "exs_server_stats": (ctypes.c_int, [_P] + [ctypes.POINTER(ctypes.c_double)] * 4
                          + [ctypes.POINTER(ctypes.c_int64)] * 3),
     "exs_server_destroy": (None, [_P]),

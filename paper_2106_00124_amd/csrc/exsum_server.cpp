@@ -84,6 +84,7 @@ struct Request {
     uint64_t ticket;
     exs_job job;
     bool generate = false;  // the server fills the input itself
+    hipEvent_t ready = nullptr;  // recorded on the caller's stream at submit: the input is written
     int fill_kind = 0;
     uint64_t seed = 0;
     int64_t lo = 0, hi = 0;
@@ -116,6 +117,14 @@ struct exs_server {
     std::atomic<bool> stop{false};
     std::thread worker;
     int device = 0;
+    // events recycled for submit/release ordering, and arena ranges whose
+    // release waits for work the caller enqueued on its own stream
+    std::vector<hipEvent_t> spare_events;
+    struct Deferred {
+        size_t off, bytes;
+        hipEvent_t ev;
+    };
+    std::vector<Deferred> deferred;
     // statistics
     std::vector<double> lat;
     int64_t completed = 0, failed = 0, max_queue = 0, elems_done = 0;
@@ -143,6 +152,36 @@ static size_t req_bytes(Request& r) {
     r.ws_bytes = FreeList::round(ws);
     r.total = r.in_bytes + r.out_bytes + r.ws_bytes;
     return r.total;
+}
+
+// An event from the pool (lock held), or a new one.
+static hipEvent_t take_event(exs_server* s) {
+    if (!s->spare_events.empty()) {
+        hipEvent_t e = s->spare_events.back();
+        s->spare_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Return the arena ranges whose caller-stream event has completed (lock held).
+static bool reap_deferred(exs_server* s) {
+    bool any = false;
+    for (size_t i = 0; i < s->deferred.size();) {
+        auto& d = s->deferred[i];
+        if (hipEventQuery(d.ev) == hipSuccess) {
+            s->fl.release(d.off, d.bytes);
+            s->spare_events.push_back(d.ev);
+            d = s->deferred.back();
+            s->deferred.pop_back();
+            any = true;
+        } else {
+            ++i;
+        }
+    }
+    return any;
 }
 
 // Admit queued requests (FIFO) while memory and a stream allow: assign
@@ -186,7 +225,9 @@ static exs_status launch(exs_server* s, Request& r) {
     char* ws = s->arena + r.off + r.in_bytes + r.out_bytes;
     hipStream_t st = s->streams[r.slot];
     exs_status rc = EXS_OK;
-    if (r.generate)
+    if (r.ready && hipStreamWaitEvent(st, r.ready, 0) != hipSuccess)
+        rc = set_error(EXS_EDEVICE, "hipStreamWaitEvent failed");
+    if (rc == EXS_OK && r.generate)
         rc = exs_fill((void*)r.job.in_dev, r.elems, r.job.dtype, r.fill_kind, r.seed, r.lo, r.hi, st);
     if (rc == EXS_OK) rc = exs_run(&r.job, ws, r.ws_bytes, st);
     if (rc == EXS_OK && hipEventRecord(s->events[r.slot], st) != hipSuccess)
@@ -222,11 +263,12 @@ static void worker_loop(exs_server* s) {
     while (!s->stop.load()) {
         const bool busy = std::any_of(s->slot_owner.begin(), s->slot_owner.end(),
                                       [](uint64_t t) { return t != 0; });
-        if (!busy && s->queue.empty()) {
+        if (!busy && s->queue.empty() && s->deferred.empty()) {
             s->cv.wait_for(lk, std::chrono::milliseconds(5));
             continue;
         }
-        const bool freed = retire(s);
+        const bool reaped = reap_deferred(s);
+        const bool freed = retire(s) || reaped;
         std::vector<Request*> go = admit(s);
         if (freed) s->cv.notify_all();
         lk.unlock();
@@ -238,6 +280,11 @@ static void worker_loop(exs_server* s) {
         lk.lock();
         for (auto& pr : res) {
             Request& r = *pr.first;
+            if (r.ready) {
+                // the wait is enqueued (or the launch failed): the event can be reused
+                s->spare_events.push_back(r.ready);
+                r.ready = nullptr;
+            }
             if (pr.second == EXS_OK) {
                 r.launched = true;
             } else {
@@ -262,13 +309,23 @@ static bool head_fits(exs_server* s) {
     return false;
 }
 
-static exs_status submit_common(exs_server* s, Request&& r, uint64_t* ticket) {
+static exs_status submit_common(exs_server* s, Request&& r, uint64_t* ticket, bool wait_caller,
+                                void* caller_stream) {
     exs_status st = validate_job(&r.job, false);
     if (st != EXS_OK) return st;
     if (!r.generate && !r.job.in_dev) return set_error(EXS_EINVAL, "in_dev is NULL");
     if (req_bytes(r) > s->budget)
         return set_error(EXS_ENOMEM, "request larger than the whole HBM budget");
     std::lock_guard<std::mutex> g(s->mu);
+    if (wait_caller) {
+        // the request's work starts only after the caller's stream has reached
+        // this point (the input is written there)
+        r.ready = take_event(s);
+        if (!r.ready || hipEventRecord(r.ready, (hipStream_t)caller_stream) != hipSuccess) {
+            if (r.ready) s->spare_events.push_back(r.ready);
+            return set_error(EXS_EDEVICE, "cannot record the input event on the caller's stream");
+        }
+    }
     r.ticket = s->next_ticket++;
     r.t_submit = Clock::now();
     if (!s->have_first) {
@@ -319,11 +376,11 @@ exs_status exs_server_create(size_t hbm_budget, int32_t max_inflight, exs_server
     return EXS_OK;
 }
 
-exs_status exs_server_submit(exs_server* s, const exs_job* job, uint64_t* ticket) {
+exs_status exs_server_submit(exs_server* s, const exs_job* job, void* stream, uint64_t* ticket) {
     if (!s || !job || !ticket) return set_error(EXS_EINVAL, "NULL argument");
     Request r;
     r.job = *job;
-    return submit_common(s, std::move(r), ticket);
+    return submit_common(s, std::move(r), ticket, true, stream);
 }
 
 exs_status exs_server_submit_generated(exs_server* s, const exs_job* job, int32_t fill_kind,
@@ -340,7 +397,7 @@ exs_status exs_server_submit_generated(exs_server* s, const exs_job* job, int32_
     r.seed = seed;
     r.lo = lo;
     r.hi = hi;
-    return submit_common(s, std::move(r), ticket);
+    return submit_common(s, std::move(r), ticket, false, nullptr);
 }
 
 exs_status exs_server_poll(exs_server* s, uint64_t ticket, const void** inc_dev,
@@ -374,7 +431,8 @@ exs_status exs_server_drain(exs_server* s) {
     std::unique_lock<std::mutex> lk(s->mu);
     while (true) {
         const bool busy = std::any_of(s->slot_owner.begin(), s->slot_owner.end(),
-                                      [](uint64_t t) { return t != 0; });
+                                      [](uint64_t t) { return t != 0; }) ||
+                          !s->deferred.empty();
         if (!busy && s->queue.empty()) return EXS_OK;
         if (!busy && !head_fits(s))
             return set_error(EXS_EAGAIN,
@@ -383,7 +441,7 @@ exs_status exs_server_drain(exs_server* s) {
     }
 }
 
-exs_status exs_server_release(exs_server* s, uint64_t ticket) {
+exs_status exs_server_release(exs_server* s, uint64_t ticket, void* stream) {
     if (!s) return set_error(EXS_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> g(s->mu);
     auto it = s->reqs.find(ticket);
@@ -391,7 +449,16 @@ exs_status exs_server_release(exs_server* s, uint64_t ticket) {
     Request& r = it->second;
     if (r.state == Request::QUEUED || r.state == Request::RUNNING)
         return set_error(EXS_ENOTREADY, "request still pending");
-    if (r.state == Request::DONE) s->fl.release(r.off, r.total);
+    if (r.state == Request::DONE) {
+        // the caller may still read the outputs on its stream: the range goes
+        // back to the arena once that stream passes this point
+        hipEvent_t ev = take_event(s);
+        if (!ev || hipEventRecord(ev, (hipStream_t)stream) != hipSuccess) {
+            if (ev) s->spare_events.push_back(ev);
+            return set_error(EXS_EDEVICE, "cannot record the release event on the caller's stream");
+        }
+        s->deferred.push_back({r.off, r.total, ev});
+    }
     s->reqs.erase(it);
     s->cv.notify_all();
     return EXS_OK;
@@ -434,6 +501,13 @@ void exs_server_destroy(exs_server* s) {
         (void)hipStreamDestroy(st);
     }
     for (auto ev : s->events) (void)hipEventDestroy(ev);
+    for (auto& d : s->deferred) {
+        (void)hipEventSynchronize(d.ev);
+        (void)hipEventDestroy(d.ev);
+    }
+    for (auto ev : s->spare_events) (void)hipEventDestroy(ev);
+    for (auto& kv : s->reqs)
+        if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
     if (s->arena) (void)hipFree(s->arena);
     delete s;
 }

@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import sys
+import zlib
 
 import numpy as np
 
@@ -58,6 +59,12 @@ def compare_full(orc, a, box, op, dtype, inc, exc, what=""):
     if exc is not None:
         stats["exc"] = tolerance.check(exc, re_, dtype, op, se, what=f"{what} exc")
     return stats
+
+
+def seed_of(*params) -> int:
+    """A seed derived from the test parameters that is the same in every
+    process (Python's str hash is salted per process)."""
+    return zlib.crc32(repr(params).encode())
 
 
 def say(*args):

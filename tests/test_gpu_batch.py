@@ -139,3 +139,51 @@ def test_batch_rejects_weak_jobs():
     x = torch.zeros((16, 16), device="cuda")
     with pytest.raises(ExsError, match="EUNSUPPORTED"):
         P.Batch([(x, (2, 2), "sum", "weak")])
+
+
+def test_stated_batch_matches_oracle(orc):
+    """The stated batched workload (512 tensors: rank 2-4, dims log-uniform in
+    [16, 256] up to 2^22 elements, box sides up to 32, f32 N(0,1) / i32
+    uniform [-100, 100], + or max) in one graph launch: 2000 sampled cells of
+    every tensor's included and excluded sums, and every cell of the 32
+    largest tensors, against the oracle (bit-exact for i32 and max, the
+    per-cell f32 rule otherwise)."""
+    import torch
+    import paper_2106_00124_amd as P
+    from paper_2106_00124_amd import workloads as W
+    items = W.batch_workload()
+    assert len(items) == 512
+    host = [it.tensor() for it in items]
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in host]
+    say(f"[batch] stated workload: {len(items)} tensors, "
+        f"{sum(it.n for it in items) / 1e6:.0f} M elements")
+    B = P.Batch([(x, it.box, it.op, "both") for x, it in zip(dev, items)])
+    B.launch()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(515)
+    largest = set(sorted(range(len(items)), key=lambda i: -items[i].n)[:32])
+    for t, (it, a, (inc, exc)) in enumerate(zip(items, host, B.outputs)):
+        what = f"tensor {t} {it.shape} {it.box} {it.dtype} {it.op}"
+        if t in largest:
+            ri, re_ = orc.scale(a, it.box, it.op, it.dtype)
+            si = se = None
+            if it.dtype == "f32" and it.op == "sum":
+                si = tolerance.sigma_full(orc, a, it.box, "inc")
+                se = tolerance.sigma_full(orc, a, it.box, "exc")
+            tolerance.check(inc.cpu().numpy(), ri, it.dtype, it.op, si, what=what + " inc")
+            tolerance.check(exc.cpu().numpy(), re_, it.dtype, it.op, se, what=what + " exc")
+            continue
+        pts = np.concatenate([rng.integers(0, it.n, 2000), [0, it.n - 1]]).astype(np.int64)
+        ip = torch.from_numpy(pts).cuda()
+        gi = inc.reshape(-1)[ip].cpu().numpy()
+        ge = exc.reshape(-1)[ip].cpu().numpy()
+        ri = orc.point_inc(a, it.box, it.op, it.dtype, pts)
+        re_ = orc.point_exc(a, it.box, it.op, it.dtype, pts)
+        si = se = None
+        if it.dtype == "f32" and it.op == "sum":
+            si = tolerance.sigma_points(orc, a, it.box, "inc", pts)
+            se = tolerance.sigma_points(orc, a, it.box, "exc", pts)
+        tolerance.check(gi, ri, it.dtype, it.op, si, what=what + " inc")
+        tolerance.check(ge, re_, it.dtype, it.op, se, what=what + " exc")
+    say("[batch] stated workload checked")
+    B.close()

@@ -189,3 +189,110 @@ def test_generated_input_matches_host_twin(orc):
         tolerance.check(exc.cpu().numpy(), ref, code, op, se, what=f"gen {shape} {box} {op}")
         S.release(t)
     S.close()
+
+
+def test_input_on_caller_stream_and_clone_before_release(orc):
+    """The request waits for the caller's stream that is still writing its
+    input, and a clone of the result enqueued right before release (on the
+    stream given to release) reads the finished result, not a range that a
+    later request already reuses."""
+    import torch
+    import paper_2106_00124_amd as P
+    shape, box = (96, 80, 72), (6, 5, 4)
+    ref_host = make_input(shape, "f32", 31, "sum")
+    src = torch.from_numpy(ref_host).cuda()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    S = P.Server(hbm_budget=3 * (2 * src.numel() * 4 + P.workspace_size(
+        shape, box, torch.float32, "sum", "exc")), max_inflight=2)
+    clones = []
+    tickets = []
+    for rep in range(3):
+        x = torch.empty_like(src)
+        with torch.cuda.stream(side):
+            x.fill_(float("nan"))
+            torch.cuda._sleep(20_000_000)       # the input is written well after submit
+            x.copy_(src)
+        tickets.append(S.submit(x, box, "sum", "exc", stream=side))  # keeps x alive
+    for t in tickets:
+        while S.result(t) is None:
+            pass
+        _, exc, _ = S.result(t)
+        clones.append(exc.clone())                  # enqueued on the current stream
+        S.release(t)                                # range reused only after the clone
+        # a later request may now take the range
+        y = torch.from_numpy(make_input(shape, "f32", 32, "sum")).cuda()
+        S.submit(y, box, "sum", "exc")
+    S.drain()
+    torch.cuda.synchronize()
+    _, ref = orc.scale(ref_host, box, "sum", "f32")
+    se = tolerance.sigma_full(orc, ref_host, box, "exc")
+    for c in clones:
+        tolerance.check(c.cpu().numpy(), ref, "f32", "sum", se, what="caller-stream clone")
+    S.close()
+
+
+def _c5_sample(reqs, count, seed):
+    """Indices of a sample of the serving stream: its largest requests, those
+    with the longest box sides, and uniform draws from the rest."""
+    rng = np.random.default_rng(seed)
+    by_n = sorted(range(len(reqs)), key=lambda i: -reqs[i].n)[:6]
+    by_k = sorted(range(len(reqs)), key=lambda i: -max(reqs[i].box))[:6]
+    chosen = list(dict.fromkeys(by_n + by_k))
+    rest = [i for i in rng.permutation(len(reqs)) if i not in set(chosen)]
+    chosen += [int(i) for i in rest[:count - len(chosen)]]
+    return chosen
+
+
+def _check_sampled(orc, host, box, op, dtype, pts, got, what):
+    ref = orc.point_exc(host, box, op, dtype, pts)
+    sig = tolerance.sigma_points(orc, host, box, "exc", pts) \
+        if dtype == "f32" and op == "sum" else None
+    return tolerance.check(got, ref, dtype, op, sig, what=what)
+
+
+def test_serving_stream_sample_matches_oracle(orc):
+    """200 requests of the stated serving stream (Poisson 2000 req/s for 60 s,
+    rank 2-3, dims log-uniform in [32, 1024] up to 2^26 elements, box sides up
+    to 64, + or max), including its largest requests and its longest boxes,
+    served together; sampled cells of each result against the oracle on the
+    input regenerated on the host from the request's seed."""
+    import concurrent.futures as cf
+    import torch
+    import paper_2106_00124_amd as P
+    reqs = W.serving_workload()
+    idx = _c5_sample(reqs, 200, 606)
+    sample = [reqs[i] for i in idx]
+    assert max(r.n for r in sample) > (1 << 25)
+    assert max(max(r.box) for r in sample) == 64
+    say(f"[server] {len(sample)} requests of the serving stream, "
+        f"{sum(r.n for r in sample) / 1e6:.0f} M elements")
+    S = P.Server(hbm_budget=24 << 30, max_inflight=8)
+    tickets = [S.submit_generated(r.shape, r.box, torch.float32, r.op, "exc",
+                                  kind=W.FILL_LOGMAG, seed=r.fill_seed) for r in sample]
+    got = {}
+    pts_of = {}
+    rng = np.random.default_rng(607)
+    pending = list(zip(tickets, sample))
+    while pending:
+        t, r = pending[0]
+        res = S.result(t)
+        if res is None:
+            continue
+        pts = np.concatenate([rng.integers(0, r.n, 62), [0, r.n - 1]]).astype(np.int64)
+        got[t] = res[1].reshape(-1)[torch.from_numpy(pts).cuda()].cpu().numpy()
+        pts_of[t] = pts
+        S.release(t)
+        pending.pop(0)
+    S.close()
+
+    def one(tr):
+        t, r = tr
+        host = W.counter_fill(W.FILL_LOGMAG, "f32", r.n, r.fill_seed).reshape(r.shape)
+        _check_sampled(orc, host, r.box, r.op, "f32", pts_of[t], got[t],
+                       what=f"request {r.rid} {r.shape} {r.box} {r.op}")
+        return r.n
+
+    with cf.ThreadPoolExecutor(8) as ex:
+        done = sum(ex.map(one, zip(tickets, sample)))
+    say(f"[server] checked {len(sample)} requests ({done / 1e6:.0f} M elements)")
