@@ -116,6 +116,24 @@ exs_status exs_workspace_size(const exs_job *job, size_t *bytes);
  * this call's end.  Enqueued on `stream`; no host synchronisation. */
 exs_status exs_run(const exs_job *job, void *ws_dev, size_t ws_bytes, void *stream);
 
+/* Allocation-free variant of exs_run, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The same computation and kernels as
+ * exs_run, with the workspace taken from a static device array of
+ * EXS_NOALLOC_SCRATCH_BYTES bytes that the library holds on every GPU it runs
+ * on until the process ends.  The caller passes only the job (inputs and
+ * outputs, as for exs_run) and the stream.  Makes no hipMalloc, hipFree or
+ * other allocating call (per-kernel timing is not recorded for it); the first
+ * call on a device looks up that device's array.  A job whose
+ * exs_workspace_size exceeds EXS_NOALLOC_SCRATCH_BYTES returns EXS_ENOMEM
+ * before anything is enqueued.  Every call on one GPU uses that GPU's one
+ * array: calls whose work overlaps on the device (on different streams, or
+ * from different threads without ordering) race and corrupt each other;
+ * calls ordered on one stream are safe.  No workspace contents carry over
+ * from one call to the next. */
+#define EXS_NOALLOC_SCRATCH_BYTES (64ll << 20)
+exs_status exs_run_noalloc(const exs_job *job, void *stream);
+
 /* Human-readable name of a status, and the calling thread's last error. */
 const char *exs_status_str(exs_status s);
 const char *exs_last_error(void);

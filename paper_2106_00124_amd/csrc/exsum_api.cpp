@@ -108,6 +108,9 @@ struct TimingRec {
 };
 static std::mutex g_tmu;
 static bool g_timing = false;
+// set while the allocation-free entry point runs: its launches record no
+// timing events (creating one may allocate)
+static thread_local bool g_timing_off = false;
 static std::vector<TimingRec> g_pending;
 static std::vector<hipEvent_t> g_event_pool;
 static thread_local int g_tag = -1;
@@ -126,6 +129,7 @@ static hipEvent_t take_event() {
 }
 
 KTimer::KTimer(const char* name, hipStream_t stream) : slot(-1), st(stream) {
+    if (g_timing_off) return;
     std::lock_guard<std::mutex> g(g_tmu);
     if (!g_timing) return;
     std::string nm(name);
@@ -248,6 +252,36 @@ static exs_status dispatch(const exs_job* job, Arena& ar, hipStream_t st) {
     return set_error(EXS_EINVAL, "unknown dtype");
 }
 
+// ---------------------------------------------------------------------------
+// Workspace of the allocation-free entry point: one file-scope device array
+// per GPU, found through hipGetSymbolAddress (the array's name in host code
+// is only a stand-in, not a device address).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[EXS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of this GPU's scratch array, looked up once per device
+// with that device current.
+static exs_status scratch_for_current_device(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return set_error(EXS_EDEVICE, "no current HIP device (or device index >= 64)");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(EXS_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") +
+                                              hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return EXS_OK;
+}
+
 }  // namespace exs
 
 using namespace exs;
@@ -283,6 +317,37 @@ exs_status exs_run(const exs_job* job, void* ws, size_t ws_bytes, void* stream) 
     ar.cap = ws_bytes;
     hipStream_t st = (hipStream_t)stream;
     s = dispatch(job, ar, st);
+    set_timing_tag(-1);
+    if (s != EXS_OK) return s;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return set_error(EXS_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return EXS_OK;
+}
+
+exs_status exs_run_noalloc(const exs_job* job, void* stream) {
+    exs_status s = validate_job(job, true);
+    if (s != EXS_OK) return s;
+    size_t need = 0;
+    s = exs_workspace_size(job, &need);
+    if (s != EXS_OK) return s;
+    if (need > (size_t)EXS_NOALLOC_SCRATCH_BYTES)
+        return set_error(EXS_ENOMEM, "exs_run_noalloc: this job needs " + std::to_string(need) +
+                                         " bytes of workspace, more than the " +
+                                         std::to_string((long long)EXS_NOALLOC_SCRATCH_BYTES) +
+                                         "-byte static scratch; use exs_run with a workspace");
+    void* ws = nullptr;
+    s = scratch_for_current_device(&ws);
+    if (s != EXS_OK) return s;
+    // nothing in the workspace has to start at zero: every kernel writes its
+    // scratch before reading it
+    Arena ar;
+    ar.dry = false;
+    ar.base = (char*)ws;
+    ar.cap = (size_t)EXS_NOALLOC_SCRATCH_BYTES;
+    g_timing_off = true;
+    s = dispatch(job, ar, (hipStream_t)stream);
+    g_timing_off = false;
     set_timing_tag(-1);
     if (s != EXS_OK) return s;
     hipError_t e = hipGetLastError();
