@@ -41,7 +41,10 @@ def parse():
                         "128x128x64x64 int32)")
     p.add_argument("--sweep-d", action="store_true",
                    help="instead of the headline step: excluded sums of fp32 tensors of about "
-                        "2^24 elements for d = 1..8, box side 8 (strong and weak, +)")
+                        "2^21, 2^24 and 2^27 elements for d = 1..8, box side 8 (strong and "
+                        "weak, +)")
+    p.add_argument("--sweep-log2n", type=int, nargs="+", default=[21, 24, 27],
+                   help="log2 of the element counts of the rank sweep")
     p.add_argument("--sweep-n", action="store_true",
                    help="instead of the headline step: excluded sums of fp32 cubes n^3 for "
                         "n = 64..640, box 16^3, + (time per element against N)")
@@ -407,11 +410,12 @@ def main():
 
 
 def sweep_d(args, P, torch, np):
-    """Scaling in the rank d: fp32 N(0,1) (device counter fill) tensors of
-    about 2^24 elements, n_i = round(2^(24/d)), box side min(8, n_i); included
-    and excluded sums under + by the box-complement path (strong) and by
-    total - included (weak).  Each d is checked at sampled cells against the
-    oracle."""
+    """Scaling in the rank d (the paper's higher-dimension experiment): fp32
+    tensors (device counter fill, unit variance) of N = n^d elements with
+    n = round(N^(1/d)) for N about 2^21, 2^24 and 2^27 and d = 1..8, box side
+    min(8, n) on every axis; included and excluded sums under + by the
+    box-complement path (strong) and by total - included (weak).  Every
+    configuration is checked at sampled cells against the oracle."""
     import oracle
     from tests import tolerance
     from paper_2106_00124_amd import workloads as W
@@ -419,50 +423,66 @@ def sweep_d(args, P, torch, np):
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     rows = []
-    for d in range(1, 9):
-        n = max(2, int(round(2 ** (24 / d))))
-        shape = (n,) * d
-        box = tuple(min(8, v) for v in shape)
-        N = n ** d
-        x = torch.empty(shape, dtype=torch.float32, device=dev)
-        P.fill(x, W.FILL_NORMALISH, 100 + d)
-        ws_b = max(P.workspace_size(shape, box, torch.float32, "sum", m) for m in ("both", "both_weak"))
-        ws = torch.empty(max(ws_b, 1), dtype=torch.uint8, device=dev)
-        inc, exc = torch.empty_like(x), torch.empty_like(x)
-        res = {"d": d, "shape": list(shape), "box": list(box), "elements": N}
-        for mode in ("both", "both_weak"):
-            for _ in range(2):
-                P.run(x, box, "sum", mode, inc_out=inc, exc_out=exc, workspace=ws, stream=stream)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            reps = max(3, args.steps)
-            e0.record(stream)
-            for _ in range(reps):
-                P.run(x, box, "sum", mode, inc_out=inc, exc_out=exc, workspace=ws, stream=stream)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / reps
-            key = "strong" if mode == "both" else "weak"
-            res[key + "_ms"] = round(ms, 4)
-            res[key + "_gelem_per_s"] = round(N / (ms * 1e-3) / 1e9, 2)
-            # sampled check against the oracle (the input regenerated on the host)
-            host = W.counter_fill(W.FILL_NORMALISH, "f32", N, 100 + d).reshape(shape)
-            pts = np.random.default_rng(d).integers(0, N, 16)
-            got = exc.reshape(-1)[torch.from_numpy(pts).to(dev)].cpu().numpy()
-            ref = o.point_exc(host, box, "sum", "f32", pts)
-            sig = tolerance.sigma_points(o, host, box, "exc", pts)
-            try:
-                tolerance.check(got, ref, "f32", "sum", sig)
-                res[key + "_check"] = "ok"
-            except AssertionError as err:
-                res[key + "_check"] = str(err)[:120]
-        log(f"d={d} n={n} strong {res['strong_ms']:.3f} ms weak {res['weak_ms']:.3f} ms")
-        rows.append(res)
-        del x, inc, exc, ws
-        torch.cuda.empty_cache()
-    print(json.dumps({"metric": "excluded-sum Gelem/s vs rank d (about 2^24 fp32 elements, "
-                                "box side 8, +)", "unit": "Gelem/s", "n_gpus": 1,
+    for e2 in args.sweep_log2n:
+        for d in range(1, 9):
+            n = max(2, int(round(2 ** (e2 / d))))
+            shape = (n,) * d
+            box = tuple(min(8, v) for v in shape)
+            N = n ** d
+            seed = 100 * e2 + d
+            x = torch.empty(shape, dtype=torch.float32, device=dev)
+            P.fill(x, W.FILL_NORMALISH, seed)
+            ws_b = max(P.workspace_size(shape, box, torch.float32, "sum", m)
+                       for m in ("both", "both_weak"))
+            ws = torch.empty(max(ws_b, 1), dtype=torch.uint8, device=dev)
+            inc, exc = torch.empty_like(x), torch.empty_like(x)
+            res = {"log2_target": e2, "d": d, "shape": list(shape), "box": list(box),
+                   "elements": N}
+            host = None
+            pts = np.random.default_rng(seed).integers(0, N, 16)
+            for mode in ("both", "both_weak"):
+                for _ in range(2):
+                    P.run(x, box, "sum", mode, inc_out=inc, exc_out=exc, workspace=ws,
+                          stream=stream)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                reps = max(3, args.steps)
+                e0.record(stream)
+                for _ in range(reps):
+                    P.run(x, box, "sum", mode, inc_out=inc, exc_out=exc, workspace=ws,
+                          stream=stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                key = "strong" if mode == "both" else "weak"
+                res[key + "_ms"] = round(ms, 4)
+                res[key + "_gelem_per_s"] = round(N / (ms * 1e-3) / 1e9, 2)
+                res[key + "_ns_per_elem"] = round(ms * 1e6 / N, 5)
+                if args.no_check:
+                    continue
+                # sampled cells against the oracle on the input regenerated
+                # on the host
+                if host is None:
+                    host = W.counter_fill(W.FILL_NORMALISH, "f32", N, seed).reshape(shape)
+                ip = torch.from_numpy(pts).to(dev)
+                gi = inc.reshape(-1)[ip].cpu().numpy()
+                ge = exc.reshape(-1)[ip].cpu().numpy()
+                try:
+                    tolerance.check(gi, o.point_inc(host, box, "sum", "f32", pts), "f32", "sum",
+                                    tolerance.sigma_points(o, host, box, "inc", pts))
+                    tolerance.check(ge, o.point_exc(host, box, "sum", "f32", pts), "f32", "sum",
+                                    tolerance.sigma_points(o, host, box, "exc", pts))
+                    res[key + "_check"] = "ok"
+                except AssertionError as err:
+                    res[key + "_check"] = str(err)[:120]
+            log(f"N~2^{e2} d={d} n={n} strong {res['strong_ms']:.3f} ms "
+                f"({res['strong_gelem_per_s']} Gelem/s) weak {res['weak_ms']:.3f} ms")
+            rows.append(res)
+            del x, inc, exc, ws, host
+            torch.cuda.empty_cache()
+    print(json.dumps({"metric": "excluded-sum Gelem/s vs rank d (fp32, N about 2^21, 2^24, "
+                                "2^27, box side 8, +)", "unit": "Gelem/s", "n_gpus": 1,
                       "data": "synthetic", "sweep": rows}), flush=True)
 
 
