@@ -26,6 +26,10 @@ Functions (their sources are cited in ``exsum_oracle.c``):
   and ``min``.
 * ``point_inc`` / ``point_exc`` / ``point_exc_direct`` -- one output at a time.
 * ``corners2d``   -- O3, 2-D corners cross-check (Sec. 1 / App. A idea).
+* ``brute_vi`` / ``scale_vi`` / ``point_inc_vi`` / ``point_exc_vi`` -- the
+  same for a struct element: (value, index) pairs under "argmax" (``op``
+  "max": the largest value, the lowest index among equal values) or "argmin"
+  ("min"); values are f32 widened to float64, indices int32 widened to int64.
 """
 from __future__ import annotations
 
@@ -84,6 +88,16 @@ def _bind(lib):
     lib.orc_total_f64.restype = ctypes.c_double
     lib.orc_total_i64.argtypes = [L, I, I, P]
     lib.orc_total_i64.restype = ctypes.c_int64
+    vi = {
+        "orc_brute_vi": [I, P, P, I, P, P, P, P, P, P],
+        "orc_scale_inc_vi": [I, P, P, I, P, P, P, P],
+        "orc_exc_cover_vi": [I, P, P, I, P, P, L, P, P, P],
+        "orc_point_inc_vi": [I, P, P, I, P, P, L, P, P, P],
+    }
+    for name, args in vi.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     return lib
@@ -251,6 +265,62 @@ class Oracle:
             return self.lib.orc_total_f64(w.size, _OP[op], p(w))
         w = np.ascontiguousarray(a, dtype=np.int64).reshape(-1)
         return self.lib.orc_total_i64(w.size, _OP[op], _DT[dtype], p(w))
+
+    # -- (value, index) pairs ---------------------------------------------
+    @staticmethod
+    def _prep_vi(values, index, k, op):
+        if op not in ("max", "min"):
+            raise ValueError("pairs take op 'max' (argmax) or 'min' (argmin)")
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        i = np.ascontiguousarray(index, dtype=np.int64)
+        if v.shape != i.shape:
+            raise ValueError("values and index must have the same shape")
+        d = v.ndim
+        k = [int(t) for t in k]
+        if not 1 <= d <= 8 or len(k) != d:
+            raise ValueError("rank 1..8 and a box of the same rank")
+        n = np.ascontiguousarray(v.shape, dtype=np.int64)
+        return d, n, np.ascontiguousarray(k, dtype=np.int64), v, i
+
+    def brute_vi(self, values, index, k, op):
+        """O1 for pairs: (inc_values, inc_index, exc_values, exc_index)."""
+        d, n, kk, v, i = self._prep_vi(values, index, k, op)
+        out = [np.empty(v.shape, np.float64), np.empty(v.shape, np.int64),
+               np.empty(v.shape, np.float64), np.empty(v.shape, np.int64)]
+        p = self._p
+        self._check(self.lib.orc_brute_vi(d, p(n), p(kk), _OP[op], p(v), p(i), *map(p, out)),
+                    "brute_vi")
+        return tuple(out)
+
+    def scale_vi(self, values, index, k, op):
+        """O2 for pairs: nested windows (included), half-space cover (excluded)."""
+        d, n, kk, v, i = self._prep_vi(values, index, k, op)
+        out = [np.empty(v.shape, np.float64), np.empty(v.shape, np.int64),
+               np.empty(v.shape, np.float64), np.empty(v.shape, np.int64)]
+        p = self._p
+        self._check(self.lib.orc_scale_inc_vi(d, p(n), p(kk), _OP[op], p(v), p(i), p(out[0]),
+                                              p(out[1])), "scale_inc_vi")
+        self._check(self.lib.orc_exc_cover_vi(d, p(n), p(kk), _OP[op], p(v), p(i), 0, None,
+                                              p(out[2]), p(out[3])), "exc_cover_vi")
+        return tuple(out)
+
+    def point_inc_vi(self, values, index, k, op, pts):
+        d, n, kk, v, i = self._prep_vi(values, index, k, op)
+        pts = np.ascontiguousarray(pts, dtype=np.int64)
+        ov, oi = np.empty(pts.shape[0], np.float64), np.empty(pts.shape[0], np.int64)
+        p = self._p
+        self._check(self.lib.orc_point_inc_vi(d, p(n), p(kk), _OP[op], p(v), p(i), pts.shape[0],
+                                              p(pts), p(ov), p(oi)), "point_inc_vi")
+        return ov, oi
+
+    def point_exc_vi(self, values, index, k, op, pts):
+        d, n, kk, v, i = self._prep_vi(values, index, k, op)
+        pts = np.ascontiguousarray(pts, dtype=np.int64)
+        ov, oi = np.empty(pts.shape[0], np.float64), np.empty(pts.shape[0], np.int64)
+        p = self._p
+        self._check(self.lib.orc_exc_cover_vi(d, p(n), p(kk), _OP[op], p(v), p(i), pts.shape[0],
+                                              p(pts), p(ov), p(oi)), "exc_cover_vi")
+        return ov, oi
 
     # -- O3 ----------------------------------------------------------------
     def corners2d(self, a, k, op, dtype):

@@ -47,6 +47,11 @@
  *                         idempotent, so the overlap of half-spaces does not
  *                         matter).  O(d N).
  *       orc_point_*       one output at a time (sampled checks at full size).
+ *   O1/O2 orc_*_vi        the same for a struct element: (value, index)
+ *                         pairs ordered by value with the lower index first
+ *                         among equal values; max of that total order is
+ *                         "argmax", min is "argmin" (commutative monoids, so
+ *                         the problem of Sec. 2 is defined for them).
  *   O3  orc_corners2d_*   2-D cross-check after the corners idea (Sec. 1,
  *                         "Corners Algorithm for Strong Excluded Sums"; App. A):
  *                         four disjoint vertex-anchored regions, each an
@@ -677,3 +682,175 @@ int orc_corners2d_i64(int64_t n0, int64_t n1, int64_t k0, int64_t k1, int op, in
     return 0;
 }
 #undef IDX
+
+/* ------------------------------------------------------------------------ */
+/* A struct monoid: (value, index) pairs.  The order: larger value first for */
+/* max (smaller for min); among equal values the lower index comes first.    */
+/* max / min of a total order is commutative and associative, with identity  */
+/* (-inf, INT32_MAX) for max and (+inf, INT32_MAX) for min: no pair comes     */
+/* after it.  The problem of Sec. 2 (a tensor over a monoid) applies as is.  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { double v; int64_t i; } vi_t;
+
+static vi_t vi_ident(int op) {
+    vi_t e;
+    e.v = op == ORC_MAX ? -INFINITY : INFINITY;
+    e.i = INT32_MAX;
+    return e;
+}
+/* Does a come first in the order of op (so that a op b = a)? */
+static int vi_first(int op, vi_t a, vi_t b) {
+    if (a.v != b.v) return op == ORC_MAX ? a.v > b.v : a.v < b.v;
+#if ORC_MUTANT == 7
+    return a.i > b.i; /* planted mistake: the higher index wins ties */
+#else
+    return a.i < b.i;
+#endif
+}
+static vi_t vi_op(int op, vi_t a, vi_t b) { return vi_first(op, a, b) ? a : b; }
+
+static vi_t vi_at(const double *v, const int64_t *idx, int64_t q) {
+    vi_t r;
+    r.v = v[q];
+    r.i = idx[q];
+    return r;
+}
+
+/* O1 for pairs: every (x, y) pair, inside the box or not (Sec. 2). */
+int orc_brute_vi(int d, const int64_t *n, const int64_t *k, int op, const double *v,
+                 const int64_t *idx, double *inc_v, int64_t *inc_i, double *exc_v,
+                 int64_t *exc_i) {
+    int64_t N;
+    if (check_args(d, n, k, &N) || op == ORC_SUM) return -1;
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < N; ++p) {
+        int64_t x[ORC_MAX_RANK], y[ORC_MAX_RANK];
+        unflatten(d, n, p, x);
+        vi_t si = vi_ident(op), se = vi_ident(op);
+        for (int64_t q = 0; q < N; ++q) {
+            unflatten(d, n, q, y);
+            if (in_box(d, x, k, y)) si = vi_op(op, si, vi_at(v, idx, q));
+            else                    se = vi_op(op, se, vi_at(v, idx, q));
+        }
+        inc_v[p] = si.v; inc_i[p] = si.i;
+        exc_v[p] = se.v; exc_i[p] = se.i;
+    }
+    return 0;
+}
+
+/* O2 included for pairs: nested window reductions, innermost axis first
+ * (the same nesting as orc_scale_inc_f64). */
+int orc_scale_inc_vi(int d, const int64_t *n, const int64_t *k, int op, const double *v,
+                     const int64_t *idx, double *inc_v, int64_t *inc_i) {
+    int64_t N;
+    if (check_args(d, n, k, &N) || op == ORC_SUM) return -1;
+    vi_t *cur = (vi_t *)malloc(sizeof(vi_t) * (size_t)N);
+    vi_t *nxt = (vi_t *)malloc(sizeof(vi_t) * (size_t)N);
+    if (!cur || !nxt) { free(cur); free(nxt); return -2; }
+    for (int64_t p = 0; p < N; ++p) cur[p] = vi_at(v, idx, p);
+    int64_t inner = 1;
+    for (int j = d - 1; j >= 0; --j) {
+        const int64_t len = n[j], stride = inner, outer = N / (len * inner);
+        #pragma omp parallel for collapse(2) schedule(static)
+        for (int64_t o = 0; o < outer; ++o)
+            for (int64_t i = 0; i < inner; ++i) {
+                const int64_t base = o * len * stride + i;
+                for (int64_t t = 0; t < len; ++t) {
+                    vi_t s = vi_ident(op);
+                    for (int64_t u = t; u < t + k[j] && u < len; ++u)
+                        s = vi_op(op, s, cur[base + u * stride]);
+                    nxt[base + t * stride] = s;
+                }
+            }
+        vi_t *tmp = cur; cur = nxt; nxt = tmp;
+        inner *= len;
+    }
+    for (int64_t p = 0; p < N; ++p) { inc_v[p] = cur[p].v; inc_i[p] = cur[p].i; }
+    free(cur); free(nxt);
+    return 0;
+}
+
+/* O2 excluded for pairs at the points pts (all N points when pts is NULL):
+ * the half-space cover, as for max and min (a cell outside the box lies
+ * before or after it along some axis; max / min of a total order is
+ * idempotent, so cells in several half-spaces do not matter). */
+int orc_exc_cover_vi(int d, const int64_t *n, const int64_t *k, int op, const double *v,
+                     const int64_t *idx, int64_t npts, const int64_t *pts, double *exc_v,
+                     int64_t *exc_i) {
+    int64_t N;
+    if (check_args(d, n, k, &N) || op == ORC_SUM) return -1;
+    vi_t *pre[ORC_MAX_RANK] = {0}, *suf[ORC_MAX_RANK] = {0};
+    int rc = 0;
+    const vi_t e = vi_ident(op);
+    for (int j = 0; j < d && !rc; ++j) {
+        pre[j] = (vi_t *)malloc(sizeof(vi_t) * (size_t)(n[j] + 1));
+        suf[j] = (vi_t *)malloc(sizeof(vi_t) * (size_t)(n[j] + 1));
+        if (!pre[j] || !suf[j]) { rc = -2; break; }
+        /* slab reductions over y_j == t, then prefixes (y_j < t) and
+         * suffixes (y_j >= t) of them */
+        vi_t *slab = suf[j];
+        for (int64_t t = 0; t <= n[j]; ++t) slab[t] = e;
+        int64_t inner = 1;
+        for (int m = j + 1; m < d; ++m) inner *= n[m];
+        for (int64_t p = 0; p < N; ++p) {
+            const int64_t t = (p / inner) % n[j];
+            slab[t] = vi_op(op, slab[t], vi_at(v, idx, p));
+        }
+        pre[j][0] = e;
+        for (int64_t t = 0; t < n[j]; ++t) pre[j][t + 1] = vi_op(op, pre[j][t], slab[t]);
+        for (int64_t t = n[j] - 1; t >= 0; --t) slab[t] = vi_op(op, slab[t], slab[t + 1]);
+    }
+    if (!rc) {
+        const int64_t cnt = pts ? npts : N;
+        #pragma omp parallel for schedule(static)
+        for (int64_t s = 0; s < cnt; ++s) {
+            int64_t x[ORC_MAX_RANK];
+            unflatten(d, n, pts ? pts[s] : s, x);
+            vi_t m = e;
+            for (int j = 0; j < d; ++j) {
+                const int64_t hs = x[j] + k[j] < n[j] ? x[j] + k[j] : n[j];
+                m = vi_op(op, m, pre[j][x[j]]);
+                m = vi_op(op, m, suf[j][hs]);
+            }
+            exc_v[s] = m.v;
+            exc_i[s] = m.i;
+        }
+    }
+    for (int j = 0; j < d; ++j) { free(pre[j]); free(suf[j]); }
+    return rc;
+}
+
+/* Included pairs at the points pts: a direct reduction over each box. */
+int orc_point_inc_vi(int d, const int64_t *n, const int64_t *k, int op, const double *v,
+                     const int64_t *idx, int64_t npts, const int64_t *pts, double *inc_v,
+                     int64_t *inc_i) {
+    int64_t N;
+    if (check_args(d, n, k, &N) || op == ORC_SUM) return -1;
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t s = 0; s < npts; ++s) {
+        int64_t x[ORC_MAX_RANK], y[ORC_MAX_RANK], hi[ORC_MAX_RANK];
+        unflatten(d, n, pts[s], x);
+        for (int i = 0; i < d; ++i) {
+            hi[i] = x[i] + k[i] < n[i] ? x[i] + k[i] : n[i];
+            y[i] = x[i];
+        }
+        vi_t acc = vi_ident(op);
+        for (;;) {
+            int64_t q = 0;
+            for (int i = 0; i < d; ++i) q = q * n[i] + y[i];
+            acc = vi_op(op, acc, vi_at(v, idx, q));
+            int i = d - 1;
+            while (i >= 0) {
+                if (++y[i] < hi[i]) break;
+                y[i] = x[i];
+                --i;
+            }
+            if (i < 0) break;
+        }
+        inc_v[s] = acc.v;
+        inc_i[s] = acc.i;
+    }
+    return 0;
+}
+

@@ -294,7 +294,81 @@ def pin_invariants(o):
             assert e[0, 0] == 0, (fn, dt)
 
 
-ALL_PINS = [pin_hand_1d, pin_hand_2d, pin_closed_forms, pin_textbook, pin_i32_wrap, pin_invariants]
+# --------------------------------------------------------------------------
+# the struct monoid: (value, index) pairs under argmax / argmin
+# --------------------------------------------------------------------------
+
+def brute_pairs_numpy(vals, idx, k, op):
+    """Tiny-input brute force with numpy reductions: per cell, the best value
+    over the masked region (box or complement), then the lowest index among
+    the cells holding it."""
+    n = vals.shape
+    grids = np.meshgrid(*[np.arange(s) for s in n], indexing="ij")
+    ident_v = -np.inf if op == "max" else np.inf
+    best = np.max if op == "max" else np.min
+    out = [np.empty(n), np.empty(n, np.int64), np.empty(n), np.empty(n, np.int64)]
+    for x in itertools.product(*[range(s) for s in n]):
+        inside = np.ones(n, bool)
+        for j, g in enumerate(grids):
+            inside &= (g >= x[j]) & (g < x[j] + k[j])
+        for slot, mask in ((0, inside), (2, ~inside)):
+            if not mask.any():
+                out[slot][x], out[slot + 1][x] = ident_v, I32_MAX
+                continue
+            bv = best(vals[mask])
+            out[slot][x] = bv
+            out[slot + 1][x] = idx[mask & (vals == bv)].min()
+    return out
+
+
+def pin_pairs(o):
+    # hand-derived 1-D case with ties (tests/golden/hand_vi_1d_n8_k4.txt)
+    g = load_golden("hand_vi_1d_n8_k4.txt")
+    vals, k = g["A"].astype(np.float64), g["box"]
+    idx = np.arange(vals.size)
+    for op in ("max", "min"):
+        want = [g[("inc_value", op)], g[("inc_index", op)], g[("exc_value", op)],
+                g[("exc_index", op)]]
+        for fn in ("brute_vi", "scale_vi"):
+            got = getattr(o, fn)(vals, idx, k, op)
+            for a, b in zip(got, want):
+                assert np.array_equal(a, b), (fn, op, got, want)
+        pts = np.arange(vals.size)
+        pv, pi = o.point_inc_vi(vals, idx, k, op, pts)
+        ev, ei = o.point_exc_vi(vals, idx, k, op, pts)
+        assert np.array_equal(pv, want[0]) and np.array_equal(pi, want[1]), op
+        assert np.array_equal(ev, want[2]) and np.array_equal(ei, want[3]), op
+    rng = np.random.default_rng(77)
+    for shape, k in (((7,), (3,)), ((5, 6), (2, 4)), ((4, 3, 5), (2, 3, 2)),
+                     ((3, 3, 2, 3), (2, 1, 2, 3))):
+        # few distinct values (many ties), indices a permutation so that the
+        # lowest index is not the first position
+        vals = rng.integers(-2, 3, size=shape).astype(np.float64)
+        idx = rng.permutation(vals.size).reshape(shape).astype(np.int64)
+        for op in ("max", "min"):
+            want = brute_pairs_numpy(vals, idx, k, op)
+            for fn in ("brute_vi", "scale_vi"):
+                got = getattr(o, fn)(vals, idx, k, op)
+                for a, b in zip(got, want):
+                    assert np.array_equal(a, b), (fn, op, shape, k)
+            # the value part is the scalar max / min of the same regions
+            si, se = o.scale(vals, k, op, "f64")
+            got = o.scale_vi(vals, idx, k, op)
+            assert np.array_equal(got[0], si) and np.array_equal(got[2], se), (op, shape)
+            # the box and its complement cover the tensor: the better of the
+            # two is the global argmax / argmin
+            flat_v, flat_i = vals.reshape(-1), idx.reshape(-1)
+            bv = flat_v.max() if op == "max" else flat_v.min()
+            bi = flat_i[flat_v == bv].min()
+            take_inc = (got[0] > got[2]) if op == "max" else (got[0] < got[2])
+            tie = got[0] == got[2]
+            comb_v = np.where(take_inc | tie, got[0], got[2])
+            comb_i = np.where(take_inc, got[1], np.where(tie, np.minimum(got[1], got[3]), got[3]))
+            assert np.all(comb_v == bv) and np.all(comb_i == bi), (op, shape)
+
+
+ALL_PINS = [pin_hand_1d, pin_hand_2d, pin_closed_forms, pin_textbook, pin_i32_wrap, pin_invariants,
+            pin_pairs]
 
 
 def run_all(o):

@@ -68,8 +68,8 @@ def test_rejects_bad_args(orc):
 #   1 closed box (off by one at the high edge)   2 wrong identity for max
 #   3 axes reversed in the point oracle          4 no wrap of i32 sums
 #   5 suffix half-space dropped in the max cover
-#   6 wrong identity for integer min
-@pytest.mark.parametrize("mutant", [1, 2, 3, 4, 5, 6])
+#   6 wrong identity for integer min             7 the higher index wins ties of pairs
+@pytest.mark.parametrize("mutant", [1, 2, 3, 4, 5, 6, 7])
 def test_pins_catch_planted_mistakes(mutant):
     with tempfile.TemporaryDirectory() as td:
         path = oracle.build(mutant=mutant, out=os.path.join(td, f"m{mutant}.so"))
