@@ -64,7 +64,16 @@ typedef enum {
     EXS_ENOTFOUND = 7      /* unknown ticket / handle */
 } exs_status;
 
-typedef enum { EXS_F32 = 0, EXS_F64 = 1, EXS_I32 = 2, EXS_I64 = 3 } exs_dtype;
+/* EXS_VALIDX: a struct element of 8 bytes, { float value; int32_t index; }
+ * (value first, 8-byte aligned), under the operators EXS_MAX ("argmax": the
+ * largest value, and among equal values the lowest index) and EXS_MIN
+ * ("argmin": the smallest value, the lowest index among equal values).  Both
+ * are max / min of a total order, hence commutative monoids (Sec. 2 states
+ * the problem over a monoid); identity (-inf, INT32_MAX) for EXS_MAX and
+ * (+inf, INT32_MAX) for EXS_MIN.  The index field is whatever the caller
+ * stores (typically the flat position); it only breaks ties.  EXS_SUM and
+ * EXS_WEAK return EXS_EUNSUPPORTED; the batched form does not take it. */
+typedef enum { EXS_F32 = 0, EXS_F64 = 1, EXS_I32 = 2, EXS_I64 = 3, EXS_VALIDX = 4 } exs_dtype;
 typedef enum { EXS_SUM = 0, EXS_MAX = 1, EXS_MIN = 2 } exs_op;
 
 /* mode bit-mask */

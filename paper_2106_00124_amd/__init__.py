@@ -45,10 +45,13 @@ def _mode_code(mode):
     return _MODES[mode]
 
 
-def job_for(x, box, op="sum", mode="both", inc_out=None, exc_out=None):
-    """Build an ``exs_job`` for device tensor ``x`` (outputs may be None)."""
+def job_for(x, box, op="sum", mode="both", inc_out=None, exc_out=None, dtype_code=None):
+    """Build an ``exs_job`` for device tensor ``x`` (outputs may be None).
+    ``dtype_code`` overrides the element type taken from ``x.dtype`` (pairs:
+    ``_lib.VALIDX`` on a packed int64 tensor)."""
     box = [int(v) for v in box]
-    return _lib.make_job(x.dim(), _dtype_code(x.dtype), _OPS[op], _mode_code(mode),
+    code = _dtype_code(x.dtype) if dtype_code is None else dtype_code
+    return _lib.make_job(x.dim(), code, _OPS[op], _mode_code(mode),
                          list(x.shape), box, x.data_ptr(),
                          inc_out.data_ptr() if inc_out is not None else None,
                          exc_out.data_ptr() if exc_out is not None else None)
@@ -70,7 +73,7 @@ def _stream_ptr(stream):
 
 
 def run(x, box, op="sum", mode="both", inc_out=None, exc_out=None, workspace=None,
-        stream=None):
+        stream=None, dtype_code=None):
     """Included and/or excluded sums of the contiguous device tensor ``x``.
 
     Returns ``(inc, exc)`` (None for an output not requested).  The work is
@@ -88,7 +91,7 @@ def run(x, box, op="sum", mode="both", inc_out=None, exc_out=None, workspace=Non
     if m & _lib.EXCLUDED and exc_out is None:
         exc_out = torch.empty_like(x)
     j = job_for(x, box, op, m, inc_out if m & _lib.INCLUDED else None,
-                exc_out if m & _lib.EXCLUDED else None)
+                exc_out if m & _lib.EXCLUDED else None, dtype_code)
     n = ctypes.c_size_t()
     _lib.check(_lib.lib().exs_workspace_size(ctypes.byref(j), ctypes.byref(n)))
     if workspace is None or workspace.numel() < n.value:
@@ -96,6 +99,40 @@ def run(x, box, op="sum", mode="both", inc_out=None, exc_out=None, workspace=Non
     _lib.check(_lib.lib().exs_run(ctypes.byref(j), ctypes.c_void_p(workspace.data_ptr()),
                                   workspace.numel(), _stream_ptr(stream)))
     return (inc_out if m & _lib.INCLUDED else None, exc_out if m & _lib.EXCLUDED else None)
+
+
+def pack_pairs(values, index=None):
+    """(value, index) pairs as one int64 tensor of the values' shape: each
+    element holds the float32 value's bits in its low half and the int32
+    index in its high half (the { float; int32; } layout of EXS_VALIDX).
+    ``index`` defaults to the flat position."""
+    import torch
+    if values.dtype != torch.float32:
+        raise ExsError(1, "pair values must be float32")
+    if index is None:
+        index = torch.arange(values.numel(), dtype=torch.int32,
+                             device=values.device).reshape(values.shape)
+    both = torch.stack([values.contiguous().view(torch.int32), index.to(torch.int32)], dim=-1)
+    return both.contiguous().view(torch.int64).squeeze(-1)
+
+
+def unpack_pairs(pairs):
+    """The (values, index) tensors of packed pairs (views, no copy)."""
+    import torch
+    both = pairs.view(torch.int32).reshape(*pairs.shape, 2)
+    return both[..., 0].view(torch.float32), both[..., 1]
+
+
+def run_pairs(x, box, op="max", mode="both", inc_out=None, exc_out=None, workspace=None,
+              stream=None):
+    """Included and/or excluded "argmax" (``op="max"``) or "argmin"
+    (``op="min"``) of packed (value, index) pairs (``pack_pairs``): per cell
+    the best value over the box (or its complement) and, among equal values,
+    the lowest index.  Returns packed pairs; ``unpack_pairs`` splits them."""
+    import torch
+    if x.dtype != torch.int64:
+        raise ExsError(1, "pairs must be packed into an int64 tensor (pack_pairs)")
+    return run(x, box, op, mode, inc_out, exc_out, workspace, stream, dtype_code=_lib.VALIDX)
 
 
 FILL_NORMALISH, FILL_UNIFORM_INT, FILL_LOGMAG = 0, 1, 2

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("EXSUM_LIB", os.path.join(HERE, "libexsum.so"))
 
 MAX_RANK = 8
-F32, F64, I32, I64 = 0, 1, 2, 3
+F32, F64, I32, I64, VALIDX = 0, 1, 2, 3, 4
 SUM, MAX, MIN = 0, 1, 2
 INCLUDED, EXCLUDED, WEAK = 1, 2, 4
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE, EAGAIN, ENOTREADY, ENOTFOUND = range(8)

@@ -46,6 +46,7 @@ size_t dtype_size(int dtype) {
         case EXS_F64: return 8;
         case EXS_I32: return 4;
         case EXS_I64: return 8;
+        case EXS_VALIDX: return 8;
     }
     return 0;
 }
@@ -57,6 +58,9 @@ exs_status validate_job(const exs_job* job, bool check_ptrs) {
     if (dtype_size(job->dtype) == 0) return set_error(EXS_EINVAL, "unknown dtype");
     if (job->op != EXS_SUM && job->op != EXS_MAX && job->op != EXS_MIN)
         return set_error(EXS_EINVAL, "unknown op");
+    if (job->dtype == EXS_VALIDX && job->op == EXS_SUM)
+        return set_error(EXS_EUNSUPPORTED,
+                         "(value, index) pairs take EXS_MAX (argmax) or EXS_MIN (argmin)");
     if (job->mode == 0 || (job->mode & ~(EXS_INCLUDED | EXS_EXCLUDED | EXS_WEAK)))
         return set_error(EXS_EINVAL, "mode must be EXS_INCLUDED and/or EXS_EXCLUDED [| EXS_WEAK]");
     if (job->mode & EXS_WEAK) {
@@ -192,9 +196,12 @@ struct EagerSink {
     void segexp(const T* Gw, const T* SPX, const T* SSX, T* PX, T* SX, i64 Q, i64 M, i64 L) {
         launch_segexp<T, Op>(Gw, SPX, SSX, PX, SX, Q, M, L, st);
     }
-    void total(const T* X, i64 N, void* parts, T* tot) { launch_total<T>(X, N, parts, tot, st); }
+    // weak excluded sums need an inverse: numeric element types only
+    void total(const T* X, i64 N, void* parts, T* tot) {
+        if constexpr (std::is_arithmetic<T>::value) launch_total<T>(X, N, parts, tot, st);
+    }
     void weak_exc(const T* inc, const T* tot, T* exc, i64 N) {
-        launch_weak_exc<T>(inc, tot, exc, N, st);
+        if constexpr (std::is_arithmetic<T>::value) launch_weak_exc<T>(inc, tot, exc, N, st);
     }
     void plane_weak(const T* X, T* inc, const T* tot, T* wexc, i64 n0, i64 MID, i64 NY, i64 NX,
                     i64 k0, i64 ky, i64 kx) {
@@ -242,12 +249,26 @@ static exs_status run_dtype(const exs_job* job, Arena& ar, hipStream_t st) {
     return plan_job<T>(job, ar, sink);
 }
 
+// (value, index) pairs: max and min only
+static exs_status run_validx(const exs_job* job, Arena& ar, hipStream_t st) {
+    if (job->op == EXS_MAX) {
+        EagerSink<ValIdx, OpMax> sink{st};
+        return plan_job<ValIdx>(job, ar, sink);
+    }
+    if (job->op == EXS_MIN) {
+        EagerSink<ValIdx, OpMin> sink{st};
+        return plan_job<ValIdx>(job, ar, sink);
+    }
+    return set_error(EXS_EUNSUPPORTED, "(value, index) pairs take EXS_MAX or EXS_MIN");
+}
+
 static exs_status dispatch(const exs_job* job, Arena& ar, hipStream_t st) {
     switch (job->dtype) {
         case EXS_F32: return run_dtype<float>(job, ar, st);
         case EXS_F64: return run_dtype<double>(job, ar, st);
         case EXS_I32: return run_dtype<int>(job, ar, st);
         case EXS_I64: return run_dtype<long long>(job, ar, st);
+        case EXS_VALIDX: return run_validx(job, ar, st);
     }
     return set_error(EXS_EINVAL, "unknown dtype");
 }

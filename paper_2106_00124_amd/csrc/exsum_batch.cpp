@@ -506,6 +506,8 @@ exs_status exs_batch_create(const exs_job* jobs, int32_t n, const char* tune_cac
         exs_status s = validate_job(&b->jobs[j], true);
         if (s == EXS_OK && (b->jobs[j].mode & EXS_WEAK))
             s = set_error(EXS_EUNSUPPORTED, "weak excluded sums are not batched");
+        if (s == EXS_OK && b->jobs[j].dtype == EXS_VALIDX)
+            s = set_error(EXS_EUNSUPPORTED, "(value, index) pairs are not batched");
         if (s != EXS_OK) {
             delete b;
             return set_error(s, "job " + std::to_string(j) + ": " + exs_last_error());

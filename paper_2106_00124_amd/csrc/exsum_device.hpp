@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "exsum_internal.hpp"
+
 typedef long long i64;
 
 namespace exs {
@@ -59,8 +61,14 @@ struct OpMax {
     static __device__ __forceinline__ long long apply(long long a, long long b) {
         return a > b ? a : b;
     }
+    static __device__ __forceinline__ ValIdx apply(ValIdx a, ValIdx b) {
+        return (a.v > b.v || (a.v == b.v && a.i < b.i)) ? a : b;
+    }
 };
 template <> __device__ __forceinline__ float OpMax::id<float>() { return -__builtin_inff(); }
+template <> __device__ __forceinline__ ValIdx OpMax::id<ValIdx>() {
+    return ValIdx{-__builtin_inff(), 0x7fffffff};
+}
 template <> __device__ __forceinline__ double OpMax::id<double>() { return -__builtin_inf(); }
 template <> __device__ __forceinline__ int OpMax::id<int>() { return (int)0x80000000; }
 template <> __device__ __forceinline__ long long OpMax::id<long long>() {
@@ -80,8 +88,14 @@ struct OpMin {
     static __device__ __forceinline__ long long apply(long long a, long long b) {
         return a < b ? a : b;
     }
+    static __device__ __forceinline__ ValIdx apply(ValIdx a, ValIdx b) {
+        return (a.v < b.v || (a.v == b.v && a.i < b.i)) ? a : b;
+    }
 };
 template <> __device__ __forceinline__ float OpMin::id<float>() { return __builtin_inff(); }
+template <> __device__ __forceinline__ ValIdx OpMin::id<ValIdx>() {
+    return ValIdx{__builtin_inff(), 0x7fffffff};
+}
 template <> __device__ __forceinline__ double OpMin::id<double>() { return __builtin_inf(); }
 template <> __device__ __forceinline__ int OpMin::id<int>() { return 0x7fffffff; }
 template <> __device__ __forceinline__ long long OpMin::id<long long>() {

@@ -14,6 +14,19 @@ struct OpSum;
 struct OpMax;
 struct OpMin;
 
+// A struct element: a value with the index of where it came from.  Ordered
+// by value, and among equal values the lower index first; max of that total
+// order is "argmax" (the largest value and the first place it occurs), min is
+// "argmin".  Both are commutative and associative, so they are monoids in the
+// sense of Sec. 2 and the box-complement reordering applies; the identity is
+// the pair that comes last: (-inf, INT32_MAX) for max, (+inf, INT32_MAX) for
+// min.  Eight bytes, laid out as { float value; int32 index; }.
+struct __align__(8) ValIdx {
+    float v;
+    int i;
+};
+static_assert(sizeof(ValIdx) == 8, "ValIdx is { float; int32; }");
+
 // register bucket (power of two >= k, up to 64) of a box length; 0 = none
 inline int bucket_for(i64 k) {
     if (k <= 1) return 1;

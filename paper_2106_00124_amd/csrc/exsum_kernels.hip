@@ -710,5 +710,7 @@ EXS_INSTANTIATE(float, OpMin)
 EXS_INSTANTIATE(double, OpMin)
 EXS_INSTANTIATE(int, OpMin)
 EXS_INSTANTIATE(long long, OpMin)
+EXS_INSTANTIATE(ValIdx, OpMax)
+EXS_INSTANTIATE(ValIdx, OpMin)
 
 }  // namespace exs

@@ -118,6 +118,8 @@ EXS_TB_INST(float, OpMin)
 EXS_TB_INST(double, OpMin)
 EXS_TB_INST(int, OpMin)
 EXS_TB_INST(long long, OpMin)
+EXS_TB_INST(ValIdx, OpMax)
+EXS_TB_INST(ValIdx, OpMin)
 #undef EXS_TB_INST
 
 }  // namespace exs

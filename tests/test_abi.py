@@ -140,3 +140,26 @@ def test_weak_mode_validation():
     j = _lib.make_job(2, _lib.I32, _lib.SUM, _lib.INCLUDED | _lib.WEAK, [8, 9], [2, 3],
                       None, None, None)
     assert L.exs_workspace_size(ctypes.byref(j), ctypes.byref(n)) == _lib.EINVAL
+
+
+def test_pair_dtype_validation():
+    """(value, index) pairs: max and min plan like the 8-byte types; + and
+    weak sums are refused, and the batched form refuses pairs, all on the host."""
+    from paper_2106_00124_amd import _lib
+    L = _lib.lib()
+    n = ctypes.c_size_t()
+    for op in (_lib.MAX, _lib.MIN):
+        for d in range(1, 9):
+            j = _lib.make_job(d, _lib.VALIDX, op, _lib.INCLUDED | _lib.EXCLUDED, [5] * d,
+                              [3] * d, None, None, None)
+            assert L.exs_workspace_size(ctypes.byref(j), ctypes.byref(n)) == 0
+    j = _lib.make_job(2, _lib.VALIDX, _lib.SUM, _lib.EXCLUDED, [8, 9], [2, 3], None, None, None)
+    assert L.exs_workspace_size(ctypes.byref(j), ctypes.byref(n)) == _lib.EUNSUPPORTED
+    j = _lib.make_job(2, _lib.VALIDX, _lib.MAX, _lib.EXCLUDED | _lib.WEAK, [8, 9], [2, 3],
+                      None, None, None)
+    assert L.exs_workspace_size(ctypes.byref(j), ctypes.byref(n)) == _lib.EUNSUPPORTED
+    jobs = (_lib.ExsJob * 1)()
+    jobs[0] = _lib.make_job(2, _lib.VALIDX, _lib.MAX, _lib.EXCLUDED, [8, 9], [2, 3], 0x1000,
+                            None, 0x9000)
+    h = ctypes.c_void_p()
+    assert L.exs_batch_create(jobs, 1, None, ctypes.byref(h)) == _lib.EUNSUPPORTED
