@@ -48,6 +48,13 @@ def parse():
     p.add_argument("--sweep-n", action="store_true",
                    help="instead of the headline step: excluded sums of fp32 cubes n^3 for "
                         "n = 64..640, box 16^3, + (time per element against N)")
+    p.add_argument("--sweep-op-cost", action="store_true",
+                   help="instead of the headline step: included and excluded sums of a 3-D "
+                        "fp32 tensor under an artificially slowed + (cost steps per "
+                        "application), time per element divided by the time per application")
+    p.add_argument("--op-costs", type=int, nargs="+", default=[0, 16, 64, 256, 1024, 4096])
+    p.add_argument("--op-cost-shape", type=int, nargs="+", default=[128, 128, 128])
+    p.add_argument("--op-cost-box", type=int, nargs="+", default=[4, 4, 4])
     p.add_argument("--no-weak", action="store_true",
                    help="skip the weak excluded sums (total - included) for +")
     p.add_argument("--no-batched", action="store_true", help="skip the batched form")
@@ -179,6 +186,9 @@ def main():
         return
     if args.sweep_n:
         sweep_n(args, P, torch, np)
+        return
+    if args.sweep_op_cost:
+        sweep_op_cost(args, P, torch, np)
         return
     from paper_2106_00124_amd import _lib
     from paper_2106_00124_amd.workloads import WORKLOADS
@@ -484,6 +494,81 @@ def sweep_d(args, P, torch, np):
     print(json.dumps({"metric": "excluded-sum Gelem/s vs rank d (fp32, N about 2^21, 2^24, "
                                 "2^27, box side 8, +)", "unit": "Gelem/s", "n_gpus": 1,
                       "data": "synthetic", "sweep": rows}), flush=True)
+
+
+def sweep_op_cost(args, P, torch, np):
+    """Scaling with the cost of the operator (the paper's experiment with an
+    artificially slowed operator, Sec. 6): included and excluded sums of a
+    3-D fp32 tensor under + slowed by `cost` dependent integer steps per
+    application (exs_set_op_cost), against the time of one application per
+    element at the same parallelism (exs_op_probe).  The ratio tends to the
+    number of operator applications per element as the cost grows.  Results
+    are checked to be bit-identical to those of the plain operator."""
+    from paper_2106_00124_amd import _lib
+    from paper_2106_00124_amd import workloads as W
+    L = _lib.lib()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    shape, box = tuple(args.op_cost_shape), tuple(args.op_cost_box)
+    x = torch.empty(shape, dtype=torch.float32, device=dev)
+    P.fill(x, W.FILL_NORMALISH, 300)
+    N = x.numel()
+    ws = torch.empty(max(P.workspace_size(shape, box, torch.float32, "sum", "both"), 1),
+                     dtype=torch.uint8, device=dev)
+    probe = torch.empty_like(x)
+    reps_probe = 16
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ref = {}
+    rows = []
+    try:
+        for cost in args.op_costs:
+            _lib.check(L.exs_set_op_cost(cost))
+            res = {"cost_steps": cost}
+            for mode in ("inc", "exc", "both"):
+                inc = torch.empty_like(x)
+                exc = torch.empty_like(x)
+                reps = 5 if cost <= 256 else 2
+                ms = timed(lambda: P.run(x, box, "sum", mode, inc_out=inc, exc_out=exc,
+                                         workspace=ws, stream=stream), reps)
+                outs = [t for t, m in ((inc, "inc"), (exc, "exc")) if m in mode or mode == "both"]
+                if cost == args.op_costs[0]:
+                    ref[mode] = [t.clone() for t in outs]
+                else:
+                    res[mode + "_identical"] = all(torch.equal(a, b)
+                                                   for a, b in zip(outs, ref[mode]))
+                res[mode + "_ms"] = round(ms, 4)
+                res[mode + "_ns_per_elem"] = round(ms * 1e6 / N, 4)
+            probe.copy_(x)
+            pms = timed(lambda: _lib.check(L.exs_op_probe(ctypes.c_void_p(probe.data_ptr()), N,
+                                                          reps_probe, sp)),
+                        3 if cost <= 256 else 1)
+            op_ns = pms * 1e6 / N / reps_probe
+            res["op_ns_per_elem"] = round(op_ns, 5)
+            for mode in ("inc", "exc", "both"):
+                res[mode + "_ops_per_elem"] = round(res[mode + "_ns_per_elem"] / op_ns, 2)
+            log(f"cost {cost}: both {res['both_ms']:.3f} ms, one op per element "
+                f"{op_ns * 1e3:.3f} ps, ratio inc {res['inc_ops_per_elem']} exc "
+                f"{res['exc_ops_per_elem']} both {res['both_ops_per_elem']}")
+            rows.append(res)
+    finally:
+        L.exs_set_op_cost(0)
+    print(json.dumps({"metric": "time per element / time per operator application vs "
+                                "operator cost (3-D fp32, +)",
+                      "shape": list(shape), "box": list(box), "n_gpus": 1, "data": "synthetic",
+                      "probe_reps": reps_probe, "sweep": rows}), flush=True)
 
 
 def sweep_n(args, P, torch, np):

@@ -161,6 +161,24 @@ exs_status exs_timing_enable(int32_t on);
 exs_status exs_timing_read(int32_t max, char *names, int64_t *launches, double *total_ms,
                            int32_t *count);
 
+/* An artificially expensive operator (measurement support, after the
+ * experiment of Sec. 6, "Excluded Sums With Different Operators", which slows
+ * its operator down with a recursive Fibonacci computation of tunable size to
+ * see how the algorithms scale with the cost of op).  While cost > 0, f32 +
+ * in exs_run and exs_run_noalloc (strong included/excluded sums; not EXS_WEAK)
+ * runs through an operator that performs `cost` dependent 32-bit integer
+ * multiply-add steps in every application before returning a + b: results
+ * are unchanged, only slower.  cost = 0 restores the plain operator.
+ * Process-wide; set it only while no other call of the library runs.
+ * EXS_EINVAL for cost outside 0..2^20, EXS_EDEVICE if the device constant
+ * cannot be written. */
+exs_status exs_set_op_cost(int32_t cost);
+/* Apply that operator `reps` times to each of the n f32 elements at data_dev
+ * (data[i] <- data[i] + ... + data[i], reps terms, one thread per element),
+ * enqueued on `stream`: the time of one application per element at the
+ * parallelism of the library's kernels, to divide the time per element by. */
+exs_status exs_op_probe(void *data_dev, int64_t n, int32_t reps, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Input generation on the device (workload support, not part of the method) */
 /* ---------------------------------------------------------------------- */

@@ -54,6 +54,8 @@ SIGNATURES = {
     "exs_version": (ctypes.c_char_p, []),
     "exs_fill": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                 ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, _P]),
+    "exs_set_op_cost": (ctypes.c_int, [ctypes.c_int32]),
+    "exs_op_probe": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, _P]),
     "exs_timing_enable": (ctypes.c_int, [ctypes.c_int32]),
     "exs_timing_read": (ctypes.c_int, [ctypes.c_int32, ctypes.c_char_p,
                                        ctypes.POINTER(ctypes.c_int64),

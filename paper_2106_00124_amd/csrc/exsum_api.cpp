@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -235,8 +236,17 @@ struct EagerSink {
     }
 };
 
+// cost of the slowed fp32 + (0: the plain operator); exs_set_op_cost
+static std::atomic<int> g_op_cost{0};
+
 template <typename T>
 static exs_status run_dtype(const exs_job* job, Arena& ar, hipStream_t st) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (job->op == EXS_SUM && !(job->mode & EXS_WEAK) && g_op_cost.load() > 0) {
+            EagerSink<T, OpSlowSum> sink{st};
+            return plan_job<T>(job, ar, sink);
+        }
+    }
     if (job->op == EXS_SUM) {
         EagerSink<T, OpSum> sink{st};
         return plan_job<T>(job, ar, sink);
@@ -374,6 +384,30 @@ exs_status exs_run_noalloc(const exs_job* job, void* stream) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return set_error(EXS_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return EXS_OK;
+}
+
+exs_status exs_set_op_cost(int32_t cost) {
+    if (cost < 0 || cost > (1 << 20)) return set_error(EXS_EINVAL, "cost must be in 0..2^20");
+    const hipError_t e[5] = {slow_cost_set_kernels(cost), slow_cost_set_plane(cost),
+                             slow_cost_set_row(cost), slow_cost_set_ex1d(cost),
+                             slow_cost_set_tailbox(cost)};
+    for (hipError_t x : e)
+        if (x != hipSuccess)
+            return set_error(EXS_EDEVICE, std::string("cannot set the operator cost: ") +
+                                              hipGetErrorString(x));
+    g_op_cost.store(cost);
+    return EXS_OK;
+}
+
+exs_status exs_op_probe(void* data, int64_t n, int32_t reps, void* stream) {
+    if (n < 0 || reps < 0) return set_error(EXS_EINVAL, "n and reps must be >= 0");
+    if (n > 0 && !data) return set_error(EXS_EINVAL, "data is NULL");
+    if (n == 0) return EXS_OK;
+    launch_op_probe((float*)data, n, reps, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return set_error(EXS_EDEVICE, std::string("probe launch failed: ") + hipGetErrorString(e));
     return EXS_OK;
 }
 

@@ -102,6 +102,29 @@ template <> __device__ __forceinline__ long long OpMin::id<long long>() {
     return (long long)0x7fffffffffffffffULL;
 }
 
+// An artificially expensive + on fp32 (measurement support, after the
+// experiment of Sec. 6, "Excluded Sums With Different Operators", which slows
+// its operator down with a recursive Fibonacci computation of tunable size).
+// apply returns a + b, as OpSum does, after `g_slow_cost` dependent 32-bit
+// integer multiply-add steps whose result is kept live and then dropped, so
+// every application costs a known number of extra instructions and results
+// do not change.  Every translation unit holds its own copy of the cost
+// (internal linkage); set_slow_cost_here writes this unit's copy.
+static __constant__ int g_slow_cost;
+struct OpSlowSum : OpSum {
+    static __device__ __forceinline__ float apply(float a, float b) {
+        const float r = a + b;
+        unsigned h = __float_as_uint(r);
+        const int c = g_slow_cost;
+        for (int i = 0; i < c; ++i) h = h * 1664525u + 1013904223u;
+        asm volatile("" : : "v"(h));
+        return r;
+    }
+};
+static inline hipError_t set_slow_cost_here(int c) {
+    return hipMemcpyToSymbol(HIP_SYMBOL(g_slow_cost), &c, sizeof(c));
+}
+
 __device__ __forceinline__ i64 gtid() {
     return (i64)blockIdx.x * (i64)blockDim.x + (i64)threadIdx.x;
 }

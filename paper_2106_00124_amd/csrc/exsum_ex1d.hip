@@ -301,5 +301,8 @@ template void launch_long1d<float, OpMin>(const float*, float*, float*, i64, i64
                                           float*, float*, hipStream_t);
 template void launch_long1d<int, OpMin>(const int*, int*, int*, i64, i64, int*, int*, int*, int*,
                                         hipStream_t);
+template void launch_long1d<float, OpSlowSum>(const float*, float*, float*, i64, i64, float*,
+                                              float*, float*, float*, hipStream_t);
+hipError_t slow_cost_set_ex1d(int c) { return set_slow_cost_here(c); }
 
 }  // namespace exs

@@ -13,6 +13,16 @@ namespace exs {
 struct OpSum;
 struct OpMax;
 struct OpMin;
+struct OpSlowSum;  // fp32 + with an artificial cost per application (measurement)
+
+// per translation unit: write that unit's copy of the slowed operator's cost
+hipError_t slow_cost_set_kernels(int c);
+hipError_t slow_cost_set_plane(int c);
+hipError_t slow_cost_set_row(int c);
+hipError_t slow_cost_set_ex1d(int c);
+hipError_t slow_cost_set_tailbox(int c);
+// the slowed operator applied reps times to each of n elements (time per op)
+void launch_op_probe(float* data, i64 n, int reps, hipStream_t st);
 
 // A struct element: a value with the index of where it came from.  Ordered
 // by value, and among equal values the lower index first; max of that total

@@ -607,6 +607,26 @@ template void launch_tail_scan<float, OpMin>(const float*, float*, float*, float
                                              i64, hipStream_t);
 template void launch_tail_scan<int, OpMin>(const int*, int*, int*, int*, i64, i64, i64, i64,
                                            hipStream_t);
+template void launch_tail_scan<float, OpSlowSum>(const float*, float*, float*, float*, i64, i64,
+                                                 i64, i64, hipStream_t);
+
+hipError_t slow_cost_set_kernels(int c) { return set_slow_cost_here(c); }
+
+// reps applications of the slowed + per element, one thread per element
+__global__ __launch_bounds__(256) void k_op_probe(float* __restrict__ data, i64 n, int reps) {
+    const i64 i = gtid();
+    if (i >= n) return;
+    const float v = data[i];
+    float acc = 0.0f;
+    for (int r = 0; r < reps; ++r) acc = OpSlowSum::apply(acc, v);
+    data[i] = acc;
+}
+
+void launch_op_probe(float* data, i64 n, int reps, hipStream_t st) {
+    KTimer timer("k_op_probe", st);
+    const i64 grid = (n + 255) / 256;
+    hipLaunchKernelGGL(k_op_probe, dim3((unsigned)grid), dim3(256), 0, st, data, n, reps);
+}
 
 template <typename T, class Op>
 void launch_blockagg(const T* X, T* Ga, i64 n0, i64 M, i64 k0, i64 Q, hipStream_t st) {
@@ -710,6 +730,7 @@ EXS_INSTANTIATE(float, OpMin)
 EXS_INSTANTIATE(double, OpMin)
 EXS_INSTANTIATE(int, OpMin)
 EXS_INSTANTIATE(long long, OpMin)
+EXS_INSTANTIATE(float, OpSlowSum)
 EXS_INSTANTIATE(ValIdx, OpMax)
 EXS_INSTANTIATE(ValIdx, OpMin)
 

@@ -54,6 +54,15 @@ template void launch_plane_scan<float, OpMax>(const float*, const float*, float*
                                             i64, i64, i64, i64, i64, hipStream_t);
 template void launch_plane_scan<float, OpMin>(const float*, const float*, float*, float*, float*, float*, i64, i64,
                                             i64, i64, i64, i64, i64, hipStream_t);
+template void launch_plane_axis0<float, OpSlowSum>(const float*, const float*, const float*,
+                                                   const float*, float*, float*, i64, i64, i64,
+                                                   i64, i64, i64, i64, i64, hipStream_t);
+template void launch_plane_bdbs<float, OpSlowSum>(const float*, float*, i64, i64, i64, i64, i64,
+                                                  hipStream_t);
+template void launch_plane_scan<float, OpSlowSum>(const float*, const float*, float*, float*,
+                                                  float*, float*, i64, i64, i64, i64, i64, i64,
+                                                  i64, hipStream_t);
+hipError_t slow_cost_set_plane(int c) { return set_slow_cost_here(c); }
 template void launch_plane_weak<float, OpSum>(const float*, float*, const float*, float*, i64, i64,
                                               i64, i64, i64, i64, i64, hipStream_t);
 }  // namespace exs

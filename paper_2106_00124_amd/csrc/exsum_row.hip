@@ -27,5 +27,9 @@ template void launch_row_axis0<float, OpMin>(const float*, const float*, const f
                                              float*, float*, i64, i64, i64, i64, i64, hipStream_t);
 template void launch_row_axis0<int, OpMin>(const int*, const int*, const int*, const int*, int*,
                                            int*, i64, i64, i64, i64, i64, hipStream_t);
+template void launch_row_axis0<float, OpSlowSum>(const float*, const float*, const float*,
+                                                 const float*, float*, float*, i64, i64, i64, i64,
+                                                 i64, hipStream_t);
+hipError_t slow_cost_set_row(int c) { return set_slow_cost_here(c); }
 
 }  // namespace exs

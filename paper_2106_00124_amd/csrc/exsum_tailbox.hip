@@ -118,8 +118,11 @@ EXS_TB_INST(float, OpMin)
 EXS_TB_INST(double, OpMin)
 EXS_TB_INST(int, OpMin)
 EXS_TB_INST(long long, OpMin)
+EXS_TB_INST(float, OpSlowSum)
 EXS_TB_INST(ValIdx, OpMax)
 EXS_TB_INST(ValIdx, OpMin)
 #undef EXS_TB_INST
+
+hipError_t slow_cost_set_tailbox(int c) { return set_slow_cost_here(c); }
 
 }  // namespace exs
