@@ -259,12 +259,12 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
         c_pre = ar.take<T>(nc);
         c_suf = ar.take<T>(nc);
     }
-    // fused levels with at most 32 blocks take their block scans in the same
+    // fused levels with at most 64 blocks take their block scans in the same
     // pass as the box-sums of the trailing axes
     const bool p2ok =
         d >= 3 && plane2_eligible(n[d - 2], n[d - 1], k[d - 2], k[d - 1], (int)sizeof(T));
     bool scan[EXS_MAX_RANK] = {};
-    for (int j = 0; j < d; ++j) scan[j] = fz[j] && Q[j] <= 32 && p2ok;
+    for (int j = 0; j < d; ++j) scan[j] = fz[j] && Q[j] <= 64 && p2ok;
     // the rank-3 level d - 3, when it takes that pass, also reduces R_{d-2}
     // over the blocks of level d - 2 (its tiles hold whole blocks); when that
     // table is small one workgroup finishes the last two levels from it

@@ -576,8 +576,8 @@ __global__ void __launch_bounds__(1024) k_plane_bdbs(Plane2Args a) {
 // block axis q without storing them:
 //   PX[q, m] = op of Gw[q', m] for q' < q,  SX[q, m] = op of Gw[q', m] for q' > q,
 //   R[m]     = op of Ga[q, m] over all q (the reduction that feeds the next level).
-// One workgroup owns a tile for all Q <= QMAX planes; the box-summed values
-// of its points stay in registers.
+// One workgroup owns a tile for all Q <= QMAX planes (QMAX = 32 or 64); the
+// box-summed values of its points stay in registers.
 // ---------------------------------------------------------------------------
 struct PlaneScanArgs {
     const void* G;   // (Q, MID, NY, NX)
@@ -779,8 +779,11 @@ void launch_plane_scan_kp(PlaneScanArgs pa, hipStream_t st) {
     if (pa.Q == 32 && pa.G == pa.Ga)
         hipLaunchKernelGGL((k_plane_scan<T, Op, KP, 32, true>), dim3((unsigned)grid), dim3(C::NT),
                            0, st, pa);
-    else
+    else if (pa.Q <= 32)
         hipLaunchKernelGGL((k_plane_scan<T, Op, KP, 32, false>), dim3((unsigned)grid),
+                           dim3(C::NT), 0, st, pa);
+    else
+        hipLaunchKernelGGL((k_plane_scan<T, Op, KP, 64, false>), dim3((unsigned)grid),
                            dim3(C::NT), 0, st, pa);
 }
 

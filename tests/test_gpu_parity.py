@@ -91,9 +91,15 @@ PLANE_CASES = [
     ((50, 20, 100), (12, 2, 16)),
     ((33, 64, 31), (16, 5, 3)),
     ((65, 47, 48), (13, 16, 9)),
-    # 32 blocks along axis 0 (one-pass block scans) and 33 (separate passes)
+    # 32 blocks along axis 0 and 33, 40, 63 and 64 (one-pass block scans with
+    # the 32- and 64-block register tables), 65 (separate passes)
     ((64, 40, 40), (2, 5, 5)),
     ((66, 40, 40), (2, 5, 5)),
+    ((160, 36, 41), (4, 5, 6)),
+    ((630, 20, 40), (10, 3, 4)),
+    ((256, 33, 20), (4, 16, 2)),
+    ((130, 40, 40), (2, 5, 5)),
+    ((96, 8, 40, 30), (2, 2, 5, 3)),
     # levels 1 and 2 from the level-0 scan's block aggregates in one
     # workgroup: the largest table it takes (32 blocks x 512) and one block
     # more (the separate passes), the longest last level it takes (4096) and
