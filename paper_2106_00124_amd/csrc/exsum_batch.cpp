@@ -97,7 +97,7 @@ struct ListSink {
             push(s, kb);
             return;
         }
-        s.kind = SK_BDBS;
+        s.kind = narrow_ok(O * n * I, (int)sizeof(T), kb) ? SK_BDBS : SK_BDBSW;
         const i64 nb = (n + k - 1) / k, cols = O * I;
         i64 nch = (cfg.min_tasks + cols - 1) / cols;
         if (nch > nb) nch = nb;
@@ -179,7 +179,7 @@ struct ListSink {
             return;
         }
         Step s{};
-        s.kind = SK_AX0;
+        s.kind = narrow_ok(n0 * M, (int)sizeof(T), kb) ? SK_AX0 : SK_AX0W;
         s.k = (int)k0;
         s.in0 = W;
         s.in1 = PX;
@@ -236,7 +236,8 @@ struct Launch {
     int dtype, op, kind, kb;
     size_t first;  // index of the first step in the device array
     int nsteps;
-    i64 total;
+    size_t table;  // offset of its chunk table (task table for row tasks)
+    i64 units;     // chunks of WL_CHUNK tasks (tasks, for row tasks)
     size_t lds;    // dynamic LDS bytes per workgroup (row tasks)
 };
 
@@ -255,6 +256,8 @@ struct exs_batch {
     std::vector<std::vector<Launch>> phases;
     Step* dev_steps = nullptr;
     size_t dev_cap = 0;
+    int* dev_table = nullptr;  // per launch: the step of every chunk (or row task)
+    size_t table_cap = 0;
     i64 items = 0;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -286,6 +289,7 @@ static exs_status build(exs_batch* b, void* ws, const TuneCfg& cfg) {
         maxlen = std::max(maxlen, recs[j].size());
     }
     std::vector<Step> all;
+    std::vector<int> table;
     b->phases.assign(maxlen, {});
     b->items = 0;
     for (size_t p = 0; p < maxlen; ++p) {
@@ -301,22 +305,33 @@ static exs_status build(exs_batch* b, void* ws, const TuneCfg& cfg) {
             L.kb = std::get<3>(g.first);
             L.first = all.size();
             L.nsteps = (int)g.second.size();
+            L.table = table.size();
+            // row tasks: one table entry per task; other kinds: every step
+            // starts at a chunk boundary and each chunk names its step
+            const bool rows = L.kind == SK_BDBSR;
             i64 tb = 0;
             L.lds = 0;
             for (const Rec* r : g.second) {
                 Step s = r->s;
                 s.task_begin = tb;
-                tb += s.ntasks;
+                const i64 span = rows ? s.ntasks : (s.ntasks + WL_CHUNK - 1) / WL_CHUNK * WL_CHUNK;
+                tb += span;
+                const int local = (int)(all.size() - L.first);
+                for (i64 u = 0; u < (rows ? span : span / WL_CHUNK); ++u) table.push_back(local);
                 all.push_back(s);
-                if (s.kind == SK_BDBSR)
+                if (rows)
                     L.lds = std::max(L.lds, (size_t)ROWS_PER_TASK * rows_pitch(s.cb, s.k) *
                                                 dtype_size(L.dtype));
             }
-            L.total = tb;
+            L.units = rows ? tb : tb / WL_CHUNK;
             b->items += (i64)g.second.size();
             b->phases[p].push_back(L);
         }
     }
+    // the tables are rewritten in place: earlier launches of this batch, on
+    // any stream, must be done with them
+    if ((b->dev_steps || b->dev_table) && hipDeviceSynchronize() != hipSuccess)
+        return set_error(EXS_EDEVICE, "hipDeviceSynchronize failed before rewriting the tables");
     const size_t bytes = all.size() * sizeof(Step);
     if (bytes > b->dev_cap) {
         if (b->dev_steps) (void)hipFree(b->dev_steps);
@@ -328,6 +343,17 @@ static exs_status build(exs_batch* b, void* ws, const TuneCfg& cfg) {
     }
     if (bytes && hipMemcpy(b->dev_steps, all.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
         return set_error(EXS_EDEVICE, "cannot upload the batch step table");
+    const size_t tbytes = table.size() * sizeof(int);
+    if (tbytes > b->table_cap) {
+        if (b->dev_table) (void)hipFree(b->dev_table);
+        b->dev_table = nullptr;
+        b->table_cap = 0;
+        if (hipMalloc(&b->dev_table, tbytes) != hipSuccess)
+            return set_error(EXS_ENOMEM, "cannot allocate the batch chunk table");
+        b->table_cap = tbytes;
+    }
+    if (tbytes && hipMemcpy(b->dev_table, table.data(), tbytes, hipMemcpyHostToDevice) != hipSuccess)
+        return set_error(EXS_EDEVICE, "cannot upload the batch chunk table");
     b->ws_base = ws;
     return EXS_OK;
 }
@@ -336,17 +362,12 @@ static void enqueue(exs_batch* b, const TuneCfg& cfg, hipStream_t st) {
     const i64 cap = (i64)cfg.wg_per_cu * b->num_cu;
     for (auto& ph : b->phases)
         for (auto& L : ph) {
-            i64 g;
-            if (L.kind == SK_BDBSR) {
-                // one wavefront per workgroup, one task per wavefront at a time
-                g = L.total < 4 * cap ? L.total : 4 * cap;
-            } else {
-                g = (L.total + 255) / 256;
-                if (g > cap) g = cap;
-            }
+            // one chunk (one row task) per workgroup at a time
+            i64 g = L.kind == SK_BDBSR ? (L.units < 4 * cap ? L.units : 4 * cap)
+                                       : (L.units < cap ? L.units : cap);
             if (g < 1) g = 1;
-            launch_worklist(L.dtype, L.op, L.kind, L.kb, b->dev_steps + L.first, L.nsteps, L.total,
-                            (int)g, L.lds, st);
+            launch_worklist(L.dtype, L.op, L.kind, L.kb, b->dev_steps + L.first,
+                            b->dev_table + L.table, L.units, (int)g, L.lds, st);
         }
 }
 
@@ -431,6 +452,10 @@ static exs_status autotune(exs_batch* b, const char* path) {
             return EXS_OK;
         }
     }
+    // the tuning runs read the jobs' inputs on a stream of its own: whatever
+    // the caller enqueued to produce them must be complete first
+    if (hipDeviceSynchronize() != hipSuccess)
+        return set_error(EXS_EDEVICE, "hipDeviceSynchronize failed before autotuning");
     void* ws = nullptr;
     if (b->ws_total && hipMalloc(&ws, b->ws_total) != hipSuccess)
         return set_error(EXS_ENOMEM, "cannot allocate the autotuning workspace");
@@ -609,6 +634,7 @@ void exs_batch_destroy(exs_batch* b) {
     if (!b) return;
     drop_graph(b);
     if (b->dev_steps) (void)hipFree(b->dev_steps);
+    if (b->dev_table) (void)hipFree(b->dev_table);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
 }

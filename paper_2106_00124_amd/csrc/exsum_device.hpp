@@ -130,6 +130,53 @@ __device__ __forceinline__ i64 gtid() {
 }
 
 // ---------------------------------------------------------------------------
+// Raw buffer access: a descriptor (uniform 64-bit base and byte range, in
+// SGPRs) plus a per-thread 32-bit byte offset.  Accesses past the range read
+// 0 and drop stores.  Word 3 = 0x00020000 is the gfx9-family raw format.
+// 4- and 8-byte element types.
+// ---------------------------------------------------------------------------
+typedef unsigned exs_u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned voff) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte elements");
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, T v) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte elements");
+    if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, 0, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(exs_u32x2, v), r, voff, 0, 0);
+}
+// The same with the non-temporal hint (cache-policy bit NT): for output
+// planes that nothing reads again, so that they do not evict from L2 the
+// input rows that neighbouring tiles still read as halo.
+template <typename T>
+__device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, unsigned voff, T v) {
+    static_assert(sizeof(T) == 4, "4-byte elements");
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, 0, 2);
+}
+// A byte offset no descriptor of a tensor below 2^31 bytes covers: a store
+// there is dropped.
+constexpr unsigned NOWHERE = 0x80000000u;
+// Tensors below 2^31 bytes take the "narrow" generic tasks: 32-bit byte
+// offsets into descriptors over the whole tensor (fewer registers, no
+// branches around accesses) instead of 64-bit element addresses; blocks of
+// 64 keep the 64-bit form, which needs fewer registers there.
+inline bool narrow_ok(long long elems, int es, int kb) {
+    return kb <= 32 && elems * (long long)es < (1ll << 31);
+}
+
+// ---------------------------------------------------------------------------
 // BDBS along one axis for one row (Sec. 3, "Included Sums in 1D"; App. B,
 // Fig. "Pseudocode for the 1D included sum", Lemma "Correctness in 1D").
 //
@@ -205,6 +252,64 @@ __device__ __forceinline__ void bdbs_row(const T* __restrict__ src, T* __restric
 #pragma unroll
         for (int r = KB - 1; r >= 0; --r) {
             if (r < k) { s = Op::apply(nxt[r], s); cur[r] = s; }
+        }
+    }
+}
+
+// The same for a tensor below 2^31 bytes (narrow_ok): src and dst are
+// descriptors over the whole input and output, off0 the byte offset of the
+// row's element 0 and sb the byte stride along the axis.  Every element of a
+// block is loaded (elements past the row end or the block read whatever their
+// offset points at inside the tensor, or 0 past its end) and replaced by the
+// identity; their stores go to NOWHERE.
+template <typename T, class Op, int KB>
+__device__ __forceinline__ void bdbs_row_narrow(__amdgpu_buffer_rsrc_t src,
+                                                __amdgpu_buffer_rsrc_t dst, unsigned off0,
+                                                int n, unsigned sb, int k, int b0, int b1) {
+    const T e = Op::template id<T>();
+    T cur[KB], nxt[KB];
+    // byte offsets: the block's base (per thread) plus r * sb (uniform)
+    {
+        const unsigned ob = off0 + (unsigned)(b0 * k) * sb;
+        const int lim = min(k, n - b0 * k);  // elements of the block inside the row
+#pragma unroll
+        for (int r = 0; r < KB; ++r) {
+            const T v = bload<T>(src, ob + (unsigned)r * sb);
+            cur[r] = r < lim ? v : e;
+        }
+    }
+    {
+        T s = e;
+#pragma unroll
+        for (int r = KB - 1; r >= 0; --r) {
+            s = Op::apply(cur[r], s);
+            cur[r] = s;
+        }
+    }
+    for (int b = b0; b < b1; ++b) {
+        const int base = (b + 1) * k;
+        const unsigned onx = off0 + (unsigned)base * sb, ocur = off0 + (unsigned)(b * k) * sb;
+        const int limn = min(k, n - base), limc = min(k, n - b * k);
+#pragma unroll
+        for (int r = 0; r < KB; ++r) {
+            const T v = bload<T>(src, onx + (unsigned)r * sb);
+            nxt[r] = r < limn ? v : e;
+        }
+        T p = e;
+#pragma unroll
+        for (int r = 0; r < KB; ++r) {
+            T v = cur[r];
+            if (r > 0) {
+                p = Op::apply(p, nxt[r - 1]);
+                v = Op::apply(v, p);
+            }
+            bstore<T>(dst, r < limc ? ocur + (unsigned)r * sb : NOWHERE, v);
+        }
+        T s = e;
+#pragma unroll
+        for (int r = KB - 1; r >= 0; --r) {
+            s = Op::apply(nxt[r], s);
+            cur[r] = s;
         }
     }
 }

@@ -50,9 +50,12 @@ inline int bucket_for(i64 k) {
 }
 
 // work-list launch of the batched form (exsum_worklist.hip): `steps` is a
-// device array of Step (exsum_tasks.hpp)
-void launch_worklist(int dtype, int op, int kind, int kb, const void* steps, int nsteps, i64 total,
-                     int grid, size_t lds, hipStream_t st);
+// device array of Step (exsum_tasks.hpp) whose tasks start at multiples of
+// WL_CHUNK; `table` names the step of each of the `units` chunks (of each
+// task, for the row kind SK_BDBSR)
+constexpr int WL_CHUNK = 256;
+void launch_worklist(int dtype, int op, int kind, int kb, const void* steps, const int* table,
+                     i64 units, int grid, size_t lds, hipStream_t st);
 
 // generic-path launchers (exsum_kernels.hip)
 template <typename T, class Op>

@@ -26,12 +26,14 @@
 namespace exs {
 
 // Plain kernels: one thread per task of one step (exsum_tasks.hpp).
-template <typename T, class Op, int KB>
+// NARROW: the tensor is below 2^31 bytes (32-bit offsets).
+template <typename T, class Op, int KB, bool NARROW>
 __global__ __launch_bounds__(256) void k_bdbs(const T* __restrict__ in, T* __restrict__ out,
                                               i64 O, i64 n, i64 I, int k, i64 cb,
                                               i64 nchunks) {
     const i64 idx = gtid();
-    if (idx < O * nchunks * I) task_bdbs<T, Op, KB>(in, out, O, n, I, k, cb, nchunks, idx);
+    if (idx < O * nchunks * I)
+        task_bdbs<T, Op, KB, NARROW>(in, out, O, n, I, k, cb, nchunks, idx);
 }
 
 template <typename T, class Op, int KB>
@@ -343,7 +345,7 @@ __global__ __launch_bounds__(256) void k_segexp(const T* __restrict__ Gw,
     if (i < ((Q + L - 1) / L) * M) task_segexp<T, Op>(Gw, SPX, SSX, PX, SX, Q, M, L, i);
 }
 
-template <typename T, class Op, int K0B>
+template <typename T, class Op, int K0B, bool NARROW>
 __global__ __launch_bounds__(256) void k_axis0(const T* __restrict__ W, const T* __restrict__ PX,
                                                const T* __restrict__ SX,
                                                const T* __restrict__ Trest, T* __restrict__ exc,
@@ -351,7 +353,7 @@ __global__ __launch_bounds__(256) void k_axis0(const T* __restrict__ W, const T*
                                                i64 Q, i64 segblocks, i64 nseg) {
     const i64 idx = gtid();
     if (idx < nseg * M)
-        task_axis0<T, Op, K0B>(W, PX, SX, Trest, exc, inc, n0, M, k0, Q, segblocks, idx);
+        task_axis0<T, Op, K0B, NARROW>(W, PX, SX, Trest, exc, inc, n0, M, k0, Q, segblocks, idx);
 }
 
 template <typename T, class Op>
@@ -444,10 +446,15 @@ void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st
     const i64 cb = (nb + nchunks - 1) / nchunks;
     nchunks = (nb + cb - 1) / cb;
     const unsigned g = grid_for(cols * nchunks);
-#define EXS_BDBS_CASE(KB)                                                                   \
-    case KB:                                                                                \
-        hipLaunchKernelGGL((k_bdbs<T, Op, KB>), dim3(g), dim3(256), 0, st, in, out, O, n, I, \
-                           (int)k, cb, nchunks);                                            \
+    const bool nar = narrow_ok(O * n * I, (int)sizeof(T), kb);
+#define EXS_BDBS_CASE(KB)                                                                      \
+    case KB:                                                                                   \
+        if (nar)                                                                               \
+            hipLaunchKernelGGL((k_bdbs<T, Op, KB, true>), dim3(g), dim3(256), 0, st, in, out, O, \
+                               n, I, (int)k, cb, nchunks);                                     \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_bdbs<T, Op, KB, false>), dim3(g), dim3(256), 0, st, in, out, \
+                               O, n, I, (int)k, cb, nchunks);                                  \
         break;
     switch (kb) {
         EXS_BDBS_CASE(1) EXS_BDBS_CASE(2) EXS_BDBS_CASE(4) EXS_BDBS_CASE(8)
@@ -684,10 +691,15 @@ void launch_axis0(const T* W, const T* PX, const T* SX, const T* Trest, T* exc, 
     nseg = (Q + segblocks - 1) / segblocks;
     const unsigned g = grid_for(nseg * M);
     KTimer timer("k_axis0", st);
-#define EXS_AX0_CASE(KB)                                                                    \
-    case KB:                                                                                \
-        hipLaunchKernelGGL((k_axis0<T, Op, KB>), dim3(g), dim3(256), 0, st, W, PX, SX, Trest, \
-                           exc, inc, n0, M, (int)k0, Q, segblocks, nseg);                   \
+    const bool nar = narrow_ok(n0 * M, (int)sizeof(T), kb);
+#define EXS_AX0_CASE(KB)                                                                       \
+    case KB:                                                                                   \
+        if (nar)                                                                               \
+            hipLaunchKernelGGL((k_axis0<T, Op, KB, true>), dim3(g), dim3(256), 0, st, W, PX, SX, \
+                               Trest, exc, inc, n0, M, (int)k0, Q, segblocks, nseg);           \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_axis0<T, Op, KB, false>), dim3(g), dim3(256), 0, st, W, PX,    \
+                               SX, Trest, exc, inc, n0, M, (int)k0, Q, segblocks, nseg);       \
         break;
     switch (kb) {
         EXS_AX0_CASE(1) EXS_AX0_CASE(2) EXS_AX0_CASE(4) EXS_AX0_CASE(8)

@@ -121,32 +121,6 @@ __device__ __forceinline__ void bdbs_block(const T* __restrict__ src, T* __restr
     for (int r = 0; r < KP; ++r) dst[r * DS] = a0[r];
 }
 
-// Raw buffer access: a descriptor (uniform 64-bit base and byte range, in
-// SGPRs) plus a per-thread 32-bit byte offset.  Accesses past the range read
-// 0 and drop stores.  Word 3 = 0x00020000 is the gfx9-family raw format.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void* base, unsigned bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
-                                             0x00020000);
-}
-template <typename T>
-__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned voff) {
-    static_assert(sizeof(T) == 4, "4-byte elements");
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
-}
-template <typename T>
-__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, T v) {
-    static_assert(sizeof(T) == 4, "4-byte elements");
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, 0, 0);
-}
-// The same with the non-temporal hint (cache-policy bit NT): for the output
-// planes, which nothing reads again, so that they do not evict from L2 the
-// input rows that neighbouring tiles still read as halo.
-template <typename T>
-__device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, unsigned voff, T v) {
-    static_assert(sizeof(T) == 4, "4-byte elements");
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, 0, 2);
-}
-
 // WHOLE: every block of the run is exactly K0B planes (k0 == K0B, n0 a
 // multiple of k0) and K0B / P is even, so each block is a fixed sequence of
 // full rounds; otherwise rounds are sized at run time.

@@ -24,7 +24,9 @@ enum StepKind : int {
     SK_BDBSR = 6,  // BDBS along the contiguous axis through LDS (k <= 64; wavefront tasks)
     SK_SEGTOT = 7, // block scans over many blocks for few points: segment totals
     SK_SEGEXP = 8, // ... and the expansion of the scanned segment totals
-    SK_NKINDS = 9
+    SK_BDBSW = 9,  // SK_BDBS for tensors of 2^31 bytes or more (64-bit addressing)
+    SK_AX0W = 10,  // SK_AX0 for tensors of 2^31 bytes or more (64-bit addressing)
+    SK_NKINDS = 11
 };
 
 // One step of the generic path.  Pointers are device pointers; the meaning
@@ -48,7 +50,8 @@ struct Step {
 
 // BDBS along an axis of a (O, n, I) tensor: task = (o, chunk, i), i fastest
 // (coalesced whenever I >= 64); each task streams `cb` blocks of its row.
-template <typename T, class Op, int KB>
+// NARROW: the tensor is below 2^31 bytes (32-bit byte offsets, bdbs_row_narrow).
+template <typename T, class Op, int KB, bool NARROW>
 __device__ __forceinline__ void task_bdbs(const T* __restrict__ in, T* __restrict__ out, i64 O,
                                           i64 n, i64 I, int k, i64 cb, i64 nchunks, i64 idx) {
     const i64 i = idx % I;
@@ -60,7 +63,14 @@ __device__ __forceinline__ void task_bdbs(const T* __restrict__ in, T* __restric
     if (b0 >= nb || o >= O) return;
     const i64 b1 = b0 + cb < nb ? b0 + cb : nb;
     const i64 off = o * n * I + i;
-    bdbs_row<T, Op, KB>(in + off, out + off, n, I, k, b0, b1);
+    if constexpr (NARROW) {
+        const unsigned bytes = (unsigned)(O * n * I * (i64)sizeof(T));
+        bdbs_row_narrow<T, Op, KB>(buf(in, bytes), buf(out, bytes),
+                                   (unsigned)(off * (i64)sizeof(T)), (int)n,
+                                   (unsigned)(I * (i64)sizeof(T)), k, (int)b0, (int)b1);
+    } else {
+        bdbs_row<T, Op, KB>(in + off, out + off, n, I, k, b0, b1);
+    }
 }
 
 // Two-sweep BDBS for any k: the backward sweep writes the range suffixes,
@@ -174,11 +184,110 @@ __device__ __forceinline__ void task_segexp(const T* __restrict__ Gw, const T* _
 
 // Axis-0 stream (generic path): task = (run, m), m fastest; the task owns
 // point m and blocks [qa, qb) of axis 0, reading one block ahead.
+// task_axis0 for tensors below 2^31 bytes: descriptors over W (n0 x M), PX
+// and SX (Q x M), Trest (M) and the outputs, 32-bit byte offsets; block rows
+// past k0 or past the tensor are loaded from wherever their offset points
+// and replaced by the identity, their stores go to NOWHERE.
 template <typename T, class Op, int K0B>
+__device__ __forceinline__ void task_axis0_narrow(const T* __restrict__ W,
+                                                  const T* __restrict__ PX,
+                                                  const T* __restrict__ SX,
+                                                  const T* __restrict__ Trest,
+                                                  T* __restrict__ exc, T* __restrict__ inc,
+                                                  i64 n0_, i64 M_, int k0, i64 Q_,
+                                                  i64 segblocks, i64 idx) {
+    const int M = (int)M_, n0 = (int)n0_, Q = (int)Q_;
+    const int m = (int)(idx % M_), s = (int)(idx / M_);
+    const int qa = s * (int)segblocks;
+    if (qa >= Q) return;
+    const int qb = qa + (int)segblocks < Q ? qa + (int)segblocks : Q;
+    const bool do_ex = exc != nullptr, do_inc = inc != nullptr;
+    const T e = Op::template id<T>();
+    constexpr unsigned es = sizeof(T);
+    const unsigned nbytes = (unsigned)n0 * (unsigned)M * es;
+    const unsigned qbytes = (unsigned)Q * (unsigned)M * es;
+    const __amdgpu_buffer_rsrc_t rw = buf(W, nbytes);
+    const __amdgpu_buffer_rsrc_t rex = buf(exc, do_ex ? nbytes : 0u);
+    const __amdgpu_buffer_rsrc_t rin = buf(inc, do_inc ? nbytes : 0u);
+    const unsigned rowb = (unsigned)M * es;   // bytes between rows along axis 0
+    const unsigned mo = (unsigned)m * es;
+
+    // w: the raw values of the block being held (its range prefixes and
+    // suffixes are formed when it is emitted); Pb: op of everything before
+    // it, with the lower-dimensional term
+    // byte offsets: the thread's base at the block start (per thread) plus
+    // r * rowb (uniform, scalar registers)
+    T w[K0B];
+    {
+        const unsigned ob = mo + (unsigned)(qa * k0) * rowb;
+        const int lim = min(k0, n0 - qa * k0);  // rows of the block inside the tensor
+#pragma unroll
+        for (int r = 0; r < K0B; ++r) {
+            const T t = bload<T>(rw, ob + (unsigned)r * rowb);
+            w[r] = r < lim ? t : e;
+        }
+    }
+    T Pb = e;
+    if (do_ex) {
+        Pb = bload<T>(buf(PX, qbytes), mo + (unsigned)qa * rowb);
+        if (Trest) Pb = Op::apply(Pb, bload<T>(buf(Trest, rowb), mo));
+    }
+    const __amdgpu_buffer_rsrc_t rsx = buf(SX, do_ex ? qbytes : 0u);
+
+    for (int q = qa; q < qb; ++q) {
+        const int nbase = (q + 1) * k0;
+        const unsigned onx = mo + (unsigned)nbase * rowb;        // block q + 1
+        const unsigned ocur = mo + (unsigned)(q * k0) * rowb;    // block q
+        const int limn = min(k0, n0 - nbase), limc = min(k0, n0 - q * k0);
+        T v[K0B];
+#pragma unroll
+        for (int r = 0; r < K0B; ++r) {
+            const T t = bload<T>(rw, onx + (unsigned)r * rowb);
+            v[r] = r < limn ? t : e;
+        }
+        T tmp[K0B];
+        if (do_ex) {
+            // the prefix before each row of block q, then the suffix from the
+            // same row of block q + 1 on (identities past k0 change nothing)
+#pragma unroll
+            for (int r = 0; r < K0B; ++r) { tmp[r] = Pb; Pb = Op::apply(Pb, w[r]); }
+            const T sxv = bload<T>(rsx, mo + (unsigned)(q + 1) * rowb);
+            T S = (q + 1 < Q) ? sxv : e;
+#pragma unroll
+            for (int r = K0B - 1; r >= 0; --r) {
+                S = Op::apply(v[r], S);
+                bstore<T>(rex, r < limc ? ocur + (unsigned)r * rowb : NOWHERE,
+                          Op::apply(tmp[r], S));
+            }
+        }
+        if (do_inc) {
+            // BDBS along axis 0: range suffix in block q, range prefix of
+            // block q + 1 up to the row before
+            T sf = e;
+#pragma unroll
+            for (int r = K0B - 1; r >= 0; --r) { sf = Op::apply(w[r], sf); tmp[r] = sf; }
+            T p = e;
+#pragma unroll
+            for (int r = 0; r < K0B; ++r) {
+                T val = tmp[r];
+                if (r > 0) { p = Op::apply(p, v[r - 1]); val = Op::apply(val, p); }
+                bstore<T>(rin, r < limc ? ocur + (unsigned)r * rowb : NOWHERE, val);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < K0B; ++r) w[r] = v[r];
+    }
+}
+
+template <typename T, class Op, int K0B, bool NARROW>
 __device__ __forceinline__ void task_axis0(const T* __restrict__ W, const T* __restrict__ PX,
                                            const T* __restrict__ SX, const T* __restrict__ Trest,
                                            T* __restrict__ exc, T* __restrict__ inc, i64 n0,
                                            i64 M, int k0, i64 Q, i64 segblocks, i64 idx) {
+    if constexpr (NARROW) {
+        task_axis0_narrow<T, Op, K0B>(W, PX, SX, Trest, exc, inc, n0, M, k0, Q, segblocks, idx);
+        return;
+    }
     const i64 m = idx % M, s = idx / M;
     const i64 qa = s * segblocks;
     if (qa >= Q) return;
@@ -387,8 +496,9 @@ __device__ __forceinline__ void task_bdbs_rows(const T* __restrict__ in, T* __re
 // for the kinds that have one).
 template <typename T, class Op, int KIND, int KB>
 __device__ __forceinline__ void run_task(const Step& s, i64 i) {
-    if constexpr (KIND == SK_BDBS)
-        task_bdbs<T, Op, KB>((const T*)s.in0, (T*)s.out0, s.O, s.n, s.I, s.k, s.cb, s.nchunks, i);
+    if constexpr (KIND == SK_BDBS || KIND == SK_BDBSW)
+        task_bdbs<T, Op, KB, KIND == SK_BDBS>((const T*)s.in0, (T*)s.out0, s.O, s.n, s.I, s.k,
+                                              s.cb, s.nchunks, i);
     else if constexpr (KIND == SK_BDBS2)
         task_bdbs2<T, Op>((const T*)s.in0, (T*)s.out0, s.n, s.I, s.k, i);
     else if constexpr (KIND == SK_AGG)
@@ -402,9 +512,10 @@ __device__ __forceinline__ void run_task(const Step& s, i64 i) {
     else if constexpr (KIND == SK_SEGEXP)
         task_segexp<T, Op>((const T*)s.in0, (const T*)s.in1, (const T*)s.in2, (T*)s.out0,
                            (T*)s.out1, s.Q, s.I, s.cb, i);
-    else if constexpr (KIND == SK_AX0)
-        task_axis0<T, Op, KB>((const T*)s.in0, (const T*)s.in1, (const T*)s.in2, (const T*)s.in3,
-                              (T*)s.out0, (T*)s.out1, s.n, s.I, s.k, s.Q, s.cb, i);
+    else if constexpr (KIND == SK_AX0 || KIND == SK_AX0W)
+        task_axis0<T, Op, KB, KIND == SK_AX0>((const T*)s.in0, (const T*)s.in1, (const T*)s.in2,
+                                              (const T*)s.in3, (T*)s.out0, (T*)s.out1, s.n, s.I,
+                                              s.k, s.Q, s.cb, i);
     else
         task_ex2<T, Op>((const T*)s.in0, (const T*)s.in3, (T*)s.out0, s.n, s.I, s.k, i);
 }
