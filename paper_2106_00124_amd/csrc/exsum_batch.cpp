@@ -86,7 +86,17 @@ struct ListSink {
             return;
         }
         const i64 rcb = I == 1 ? rows_blocks(O, n, k, ROWS_MIN_TASKS) : 0;
-        if (I == 1 && O >= ROWS_PER_TASK && rows_tasks(O, n, k, rcb) >= ROWS_MIN_TASKS) {
+        const bool rows_lds = I == 1 && O >= ROWS_PER_TASK && rows_tasks(O, n, k, rcb) >= ROWS_MIN_TASKS;
+        if (I == 1 && !rows_lds && narrow_ok(O * n, (int)sizeof(T), 32)) {
+            // rows of the contiguous axis, too few for the LDS-staged tasks:
+            // one wavefront per task, segmented scans across the lanes
+            s.kind = SK_BDBSV;
+            s.cb = wave_rows_per_task(O);
+            s.ntasks = (O + s.cb - 1) / s.cb * 64;
+            push(s, 1);
+            return;
+        }
+        if (rows_lds) {
             // rows of the contiguous axis of a large tensor: wavefront tasks
             // through LDS
             s.kind = SK_BDBSR;

@@ -195,6 +195,15 @@ inline bool narrow_ok(long long elems, int es, int kb) {
 // ---------------------------------------------------------------------------
 // Scans of the 64 lanes of a wavefront: inclusive prefix (toward higher
 // lanes) and inclusive suffix (toward lower lanes) of one value per lane.
+// Lane shuffles of 4- and 8-byte element types (struct elements included).
+template <typename T>
+__device__ __forceinline__ T wshfl(T v, int src) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __shfl(__builtin_bit_cast(int, v), src, 64));
+    else
+        return __builtin_bit_cast(T, __shfl(__builtin_bit_cast(long long, v), src, 64));
+}
+
 template <typename T, class Op>
 __device__ __forceinline__ T wave_prefix(T v, int lane) {
 #pragma unroll

@@ -36,6 +36,14 @@ __global__ __launch_bounds__(256) void k_bdbs(const T* __restrict__ in, T* __res
         task_bdbs<T, Op, KB, NARROW>(in, out, O, n, I, k, cb, nchunks, idx);
 }
 
+// BDBS along the contiguous axis: four wavefront tasks per workgroup.
+template <typename T, class Op>
+__global__ __launch_bounds__(256) void k_bdbs_wave(const T* __restrict__ in, T* __restrict__ out,
+                                                   i64 O, i64 n, int k, i64 rpt, i64 ntasks) {
+    const i64 task = ((i64)blockIdx.x * 256 + threadIdx.x) >> 6;
+    if (task < ntasks) task_bdbs_wave<T, Op>(in, out, O, n, k, rpt, task);
+}
+
 template <typename T, class Op, int KB>
 __global__ __launch_bounds__(64) void k_bdbs_rows(const T* __restrict__ in, T* __restrict__ out,
                                                   i64 O, i64 n, int k, i64 cb, i64 nchunks) {
@@ -418,7 +426,17 @@ void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st
     }
     const i64 nb = (n + k - 1) / k;
     const i64 rcb = I == 1 ? rows_blocks(O, n, k, ROWS_MIN_TASKS) : 0;
-    if (I == 1 && O >= ROWS_PER_TASK && rows_tasks(O, n, k, rcb) >= ROWS_MIN_TASKS) {
+    const bool rows_lds = I == 1 && O >= ROWS_PER_TASK && rows_tasks(O, n, k, rcb) >= ROWS_MIN_TASKS;
+    if (I == 1 && !rows_lds && narrow_ok(O * n, (int)sizeof(T), 32)) {
+        // rows of the contiguous axis, too few for the LDS-staged tasks: one
+        // wavefront per task (lanes along the row, coalesced)
+        const i64 rpt = wave_rows_per_task(O);
+        const i64 tasks = (O + rpt - 1) / rpt;
+        hipLaunchKernelGGL((k_bdbs_wave<T, Op>), dim3(grid_for(tasks * 64)), dim3(256), 0, st, in,
+                           out, O, n, (int)k, rpt, tasks);
+        return;
+    }
+    if (rows_lds) {
         // rows of the contiguous axis, enough of them to fill the GPU with
         // wavefront tasks: staged through LDS (fewer, coalesced transactions;
         // small tensors keep the one-row-per-lane kernel, which has the

@@ -26,7 +26,9 @@ enum StepKind : int {
     SK_SEGEXP = 8, // ... and the expansion of the scanned segment totals
     SK_BDBSW = 9,  // SK_BDBS for tensors of 2^31 bytes or more (64-bit addressing)
     SK_AX0W = 10,  // SK_AX0 for tensors of 2^31 bytes or more (64-bit addressing)
-    SK_NKINDS = 11
+    SK_BDBSV = 11, // BDBS along the contiguous axis, one wavefront per task (k <= 64,
+                   // tensors below 2^31 bytes); its task count is in threads
+    SK_NKINDS = 12
 };
 
 // One step of the generic path.  Pointers are device pointers; the meaning
@@ -492,6 +494,106 @@ __device__ __forceinline__ void task_bdbs_rows(const T* __restrict__ in, T* __re
     __syncthreads();  // the tile is reused by the next task of this workgroup
 }
 
+// BDBS along the contiguous axis by one wavefront per task, without LDS: a
+// task is `rpt` consecutive rows (of n elements, k <= 64), processed RB rows
+// at a time in windows of 64 columns.  Lane l holds element c0 + l of the
+// window and element c0 + 64 + l of the next one (loaded once: it becomes the
+// next window).  Range prefixes and suffixes within k-aligned blocks are
+// segmented scans across the lanes (Sec. 3: the combine needs, at x, the
+// range suffix of x's block from x and the range prefix of the next block up
+// to x + k - 1, which lies within the two windows when k <= 64); the block
+// that straddles the two windows gets the missing part of its suffix, and its
+// prefix in the second window the part in the first.  Positions past n hold
+// the identity.  Loads and stores are whole-row, coalesced.
+constexpr int WAVE_RB = 8;
+
+// Rows per wavefront task: enough tasks to fill the GPU (about 4096), a
+// multiple of WAVE_RB, at most 64 rows.
+inline i64 wave_rows_per_task(i64 O) {
+    i64 r = (O + 4095) / 4096;
+    r = (r + WAVE_RB - 1) / WAVE_RB * WAVE_RB;
+    return r < WAVE_RB ? WAVE_RB : (r > 64 ? 64 : r);
+}
+
+template <typename T, class Op>
+__device__ __forceinline__ T seg_prefix(T v, int lane, int back) {
+    // inclusive prefix over the lanes l' with l - back <= l' <= l
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T o = wshfl(v, lane >= off ? lane - off : lane);
+        if (off <= back) v = Op::apply(o, v);
+    }
+    return v;
+}
+template <typename T, class Op>
+__device__ __forceinline__ T seg_suffix(T v, int lane, int fwd) {
+    // inclusive suffix over the lanes l' with l <= l' <= l + fwd
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T o = wshfl(v, lane + off < 64 ? lane + off : lane);
+        if (off <= fwd) v = Op::apply(v, o);
+    }
+    return v;
+}
+
+template <typename T, class Op>
+__device__ __forceinline__ void task_bdbs_wave(const T* __restrict__ in, T* __restrict__ out,
+                                               i64 O, i64 n_, int k, i64 rpt, i64 task) {
+    const int lane = threadIdx.x & 63;
+    const T e = Op::template id<T>();
+    const int n = (int)n_;
+    const i64 r_begin = task * rpt;
+    const i64 r_end = r_begin + rpt < O ? r_begin + rpt : O;
+    const unsigned bytes = (unsigned)(O * n_ * (i64)sizeof(T));
+    const __amdgpu_buffer_rsrc_t rin = buf(in, bytes), rout = buf(out, bytes);
+    constexpr unsigned es = sizeof(T);
+    for (i64 r0 = r_begin; r0 < r_end; r0 += WAVE_RB) {
+        unsigned rowoff[WAVE_RB];
+        bool live[WAVE_RB];
+        T a[WAVE_RB], h[WAVE_RB];
+#pragma unroll
+        for (int j = 0; j < WAVE_RB; ++j) {
+            live[j] = r0 + j < r_end;
+            rowoff[j] = (unsigned)((r0 + j) * n_) * es;
+            const T t = bload<T>(rin, rowoff[j] + (unsigned)lane * es);
+            a[j] = live[j] && lane < n ? t : e;
+        }
+        for (int c0 = 0; c0 < n; c0 += 64) {
+            const int xa = c0 + lane, xh = c0 + 64 + lane;
+#pragma unroll
+            for (int j = 0; j < WAVE_RB; ++j) {
+                const T t = bload<T>(rin, rowoff[j] + (unsigned)xh * es);
+                h[j] = live[j] && xh < n ? t : e;
+            }
+            // block geometry of the two windows (same for every row)
+            const int oa = xa % k, oh = xh % k;          // offsets within the blocks
+            const int endB = (c0 + 63) - (c0 + 63) % k + k - 1;  // last position of the
+            const int eh = endB - (c0 + 64);                      // straddling block
+            const int y = xa + k - 1;                    // where the next block's prefix ends
+            const int ly = y - c0;                       // its lane in the 128-window
+#pragma unroll
+            for (int j = 0; j < WAVE_RB; ++j) {
+                const T pa = seg_prefix<T, Op>(a[j], lane, oa < lane ? oa : lane);
+                const T sa = seg_suffix<T, Op>(a[j], lane, (k - 1 - oa) < 63 - lane ? k - 1 - oa : 63 - lane);
+                T ph = seg_prefix<T, Op>(h[j], lane, oh < lane ? oh : lane);
+                // the straddling block: suffix part in the second window, prefix
+                // part in the first
+                const T tailB = wshfl(ph, eh >= 0 ? eh : 0);
+                const T headB = wshfl(pa, 63);
+                const bool inB = eh >= 0 && xa + (k - 1 - oa) == endB;
+                const T rs = inB ? Op::apply(sa, tailB) : sa;
+                if (eh >= 0 && lane <= eh) ph = Op::apply(headB, ph);
+                const T va = wshfl(pa, ly < 64 ? ly : 63);
+                const T vh = wshfl(ph, ly >= 64 ? ly - 64 : 0);
+                const T rp = ly < 64 ? va : vh;
+                const T o = oa == 0 ? rs : Op::apply(rs, rp);
+                bstore<T>(rout, live[j] && xa < n ? rowoff[j] + (unsigned)xa * es : NOWHERE, o);
+                a[j] = h[j];
+            }
+        }
+    }
+}
+
 // Dispatch one task of a recorded step (KB: the register bucket of the step,
 // for the kinds that have one).
 template <typename T, class Op, int KIND, int KB>
@@ -512,6 +614,8 @@ __device__ __forceinline__ void run_task(const Step& s, i64 i) {
     else if constexpr (KIND == SK_SEGEXP)
         task_segexp<T, Op>((const T*)s.in0, (const T*)s.in1, (const T*)s.in2, (T*)s.out0,
                            (T*)s.out1, s.Q, s.I, s.cb, i);
+    else if constexpr (KIND == SK_BDBSV)
+        task_bdbs_wave<T, Op>((const T*)s.in0, (T*)s.out0, s.O, s.n, s.k, s.cb, i >> 6);
     else if constexpr (KIND == SK_AX0 || KIND == SK_AX0W)
         task_axis0<T, Op, KB, KIND == SK_AX0>((const T*)s.in0, (const T*)s.in1, (const T*)s.in2,
                                               (const T*)s.in3, (T*)s.out0, (T*)s.out1, s.n, s.I,

@@ -90,6 +90,7 @@ static void launch_kind(int kind, int kb, const Step* steps, const int* table, i
         case SK_EX2: launch_kb<T, Op, SK_EX2>(kb, steps, table, units, grid, st); break;
         case SK_BDBSW: launch_kb<T, Op, SK_BDBSW>(kb, steps, table, units, grid, st); break;
         case SK_AX0W: launch_kb<T, Op, SK_AX0W>(kb, steps, table, units, grid, st); break;
+        case SK_BDBSV: launch_kb<T, Op, SK_BDBSV>(kb, steps, table, units, grid, st); break;
     }
 }
 

@@ -31,6 +31,16 @@ CASES = [
     ((200, 4096), (16, 16)),
     ((33, 300), (16, 3)),
     ((517, 64), (2, 1)),
+    # contiguous-axis box sums by wavefront segmented scans: boxes of 17 to 64
+    # on rows shorter and longer than one 64-column window, blocks straddling
+    # the windows, ragged last blocks, several row groups per task
+    ((300, 130), (3, 64)),
+    ((100, 127), (5, 63)),
+    ((70, 65), (3, 33)),
+    ((50, 200), (2, 17)),
+    ((9, 1000), (2, 64)),
+    ((40, 30, 45), (2, 3, 45)),
+    ((700, 24), (3, 24)),
     # many blocks along an axis with few points (segmented block scans)
     ((300000,), (3,)),
     ((50000, 3), (2, 2)),
