@@ -202,7 +202,9 @@ typedef struct exs_batch exs_batch;
 
 /* Plan a batch of n jobs (copied; the job pointers are bound at create time
  * and must stay valid for every launch).  tune_cache: path of the JSON
- * autotune cache to read and update, or NULL for built-in tile choices.
+ * autotune cache to read and update, or NULL for built-in tile choices; a
+ * file at that path that does not parse as such a cache is ignored and left
+ * as it is (the batch is then tuned and the result not stored).
  * The call may time candidate tile shapes on the device (autotuning), which
  * synchronises the device and writes the outputs of the jobs. */
 exs_status exs_batch_create(const exs_job *jobs, int32_t n, const char *tune_cache,

@@ -17,7 +17,8 @@
 // many chunks a row or axis-0 stream is cut into) and the persistent grid
 // size (workgroups per CU) are chosen by timing candidate settings on the
 // batch itself; the winner is cached in a JSON file keyed by a signature of
-// the batch's shapes, boxes, dtypes, operators and modes.
+// the batch's shapes, boxes, dtypes, operators and modes.  A file at that
+// path that is not such a cache is neither used nor overwritten.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -33,6 +34,7 @@
 #include "exsum_internal.hpp"
 #include "exsum_plan.hpp"
 #include "exsum_tasks.hpp"
+#include "exsum_tunecache.hpp"
 
 namespace exs {
 
@@ -382,7 +384,7 @@ static void enqueue(exs_batch* b, const TuneCfg& cfg, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Autotune cache: {"version": 1, "entries": {"<sig>": {"min_tasks": .., ..}}}
+// Autotune cache (format and parser in exsum_tunecache.hpp)
 // ---------------------------------------------------------------------------
 static std::string signature(const std::vector<exs_job>& jobs) {
     uint64_t h = 1469598103934665603ULL;  // FNV-1a over the shape description
@@ -407,58 +409,41 @@ static std::string signature(const std::vector<exs_job>& jobs) {
     return buf;
 }
 
-static std::map<std::string, std::string> read_cache(const char* path) {
-    std::map<std::string, std::string> m;
-    std::ifstream f(path);
-    if (!f) return m;
+// Cache file state: absent, a valid cache (entries read), or something else
+// (then it is neither used nor overwritten).
+enum class CacheFile { ABSENT, OK, FOREIGN };
+
+static CacheFile read_cache(const char* path, tunecache::Entries* m) {
+    std::ifstream f(path, std::ios::binary);
+    if (!f) return CacheFile::ABSENT;
     std::stringstream ss;
     ss << f.rdbuf();
-    const std::string t = ss.str();
-    size_t p = 0;
-    while ((p = t.find("\"batch-", p)) != std::string::npos) {
-        const size_t e = t.find('"', p + 1);
-        const size_t ob = t.find('{', e);
-        const size_t cb = t.find('}', ob);
-        if (e == std::string::npos || ob == std::string::npos || cb == std::string::npos) break;
-        m[t.substr(p + 1, e - p - 1)] = t.substr(ob, cb - ob + 1);
-        p = cb;
-    }
-    return m;
+    return tunecache::parse(ss.str(), m) ? CacheFile::OK : CacheFile::FOREIGN;
 }
 
-static bool parse_field(const std::string& obj, const char* key, double* v) {
-    const std::string k = std::string("\"") + key + "\"";
-    const size_t p = obj.find(k);
-    if (p == std::string::npos) return false;
-    const size_t c = obj.find(':', p);
-    if (c == std::string::npos) return false;
-    *v = std::strtod(obj.c_str() + c + 1, nullptr);
-    return true;
-}
-
-static void write_cache(const char* path, const std::map<std::string, std::string>& m) {
+static void write_cache(const char* path, const tunecache::Entries& m) {
     const std::string tmp = std::string(path) + ".tmp";
-    std::ofstream f(tmp);
-    if (!f) return;
-    f << "{\n  \"version\": 1,\n  \"entries\": {\n";
-    size_t i = 0;
-    for (auto& kv : m) {
-        f << "    \"" << kv.first << "\": " << kv.second << (++i < m.size() ? ",\n" : "\n");
+    {
+        std::ofstream f(tmp, std::ios::binary);
+        if (!f) return;
+        f << tunecache::render(m);
+        if (!f) return;
     }
-    f << "  }\n}\n";
-    f.close();
     std::rename(tmp.c_str(), path);
 }
 
 static exs_status autotune(exs_batch* b, const char* path) {
     const std::string sig = signature(b->jobs);
-    auto cache = read_cache(path);
+    tunecache::Entries cache;
+    const CacheFile state = read_cache(path, &cache);
     auto it = cache.find(sig);
     if (it != cache.end()) {
-        double mt = 0, wg = 0;
-        if (parse_field(it->second, "min_tasks", &mt) && parse_field(it->second, "wg_per_cu", &wg)) {
-            b->cfg.min_tasks = (i64)mt;
-            b->cfg.wg_per_cu = (int)wg;
+        auto mt = it->second.find("min_tasks"), wg = it->second.find("wg_per_cu");
+        // only values the tuner itself can choose are taken
+        if (mt != it->second.end() && wg != it->second.end() && mt->second >= 1 &&
+            mt->second <= (double)(1 << 30) && wg->second >= 1 && wg->second <= 64) {
+            b->cfg.min_tasks = (i64)mt->second;
+            b->cfg.wg_per_cu = (int)wg->second;
             return EXS_OK;
         }
     }
@@ -516,11 +501,12 @@ static exs_status autotune(exs_batch* b, const char* path) {
     b->ws_base = nullptr;  // the tuning build pointed into the freed workspace
     if (rc != EXS_OK) return rc;
     b->cfg = best;
-    char obj[160];
-    std::snprintf(obj, sizeof(obj), "{\"min_tasks\": %lld, \"wg_per_cu\": %d, \"ms\": %.4f}",
-                  (long long)best.min_tasks, best.wg_per_cu, best_ms);
-    cache[sig] = obj;
-    write_cache(path, cache);
+    if (state != CacheFile::FOREIGN) {
+        cache[sig] = {{"min_tasks", (double)best.min_tasks},
+                      {"wg_per_cu", (double)best.wg_per_cu},
+                      {"ms", (double)best_ms}};
+        write_cache(path, cache);
+    }
     return EXS_OK;
 }
 

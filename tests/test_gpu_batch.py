@@ -123,6 +123,21 @@ def test_autotune_cache_written_and_reused(tmp_path, orc):
                 assert np.array_equal(u, v) or u.dtype.kind == "f"
 
 
+def test_autotune_leaves_a_foreign_file_alone(tmp_path):
+    # a file at the cache path that is not a cache: tuned, not overwritten
+    items = _mixed_items(11, 5)
+    path = tmp_path / "tune.json"
+    foreign = '{"note": "} not a cache {", "entries": [1, 2]}'
+    path.write_text(foreign)
+    B, host, dev, outs = _run_batch(items, tune_cache=str(path))
+    assert path.read_text() == foreign
+    B2, _, _, outs2 = _run_batch(items)
+    for (a0, b0), (a1, b1) in zip(outs, outs2):
+        for u, v in ((a0, a1), (b0, b1)):
+            if u is not None:
+                assert np.array_equal(u, v) or u.dtype.kind == "f"
+
+
 def test_batch_rejects_invalid_job():
     import torch
     import paper_2106_00124_amd as P
