@@ -360,6 +360,13 @@ static void i_cover_free(i_cover *c) {
 }
 
 /* inc must hold the included sums (from orc_scale_inc_f64) when op is +. */
+/* 1 if k_i = n_i on every axis (the origin's box is the whole tensor). */
+static int box_covers_all(int d, const int64_t *n, const int64_t *k) {
+    for (int i = 0; i < d; ++i)
+        if (k[i] != n[i]) return 0;
+    return 1;
+}
+
 int orc_scale_exc_f64(int d, const int64_t *n, const int64_t *k, int op,
                       const double *a, const double *inc, double *exc) {
     int64_t N;
@@ -369,6 +376,11 @@ int orc_scale_exc_f64(int d, const int64_t *n, const int64_t *k, int op,
         for (int64_t p = 0; p < N; ++p) total += a[p];
         #pragma omp parallel for schedule(static)
         for (int64_t p = 0; p < N; ++p) exc[p] = total - inc[p];
+        /* With k = n on every axis the box of the origin is the whole tensor:
+         * its complement is empty, and the sum over an empty set is the
+         * identity (Sec. 2), exactly 0 -- not the rounding residue that
+         * total - inc leaves when the two sums run in different orders. */
+        if (box_covers_all(d, n, k)) exc[0] = 0.0;
         return 0;
     }
     f_cover c;

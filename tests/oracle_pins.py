@@ -292,6 +292,15 @@ def pin_invariants(o):
             assert e[0, 0] == ident_min, (fn, dt, e[0, 0])
             _, e = getattr(o, fn)(a, [3, 4], "sum", dt)
             assert e[0, 0] == 0, (fn, dt)
+    # ... also for real-valued + on data whose two orders of summation differ
+    # in rounding (total - included would leave a residue): exactly 0, by
+    # every form, and 0 at the other cells only where the brute force says so
+    a = rng.standard_normal((50, 90))
+    _, eb = o.brute(a, [50, 90], "sum", "f64")
+    _, es = o.scale(a, [50, 90], "sum", "f64")
+    ep = o.point_exc(a, [50, 90], "sum", "f64", np.array([0, 1, 90]))
+    assert eb[0, 0] == 0.0 and es[0, 0] == 0.0 and ep[0] == 0.0
+    assert ep[1] != 0.0 and ep[2] != 0.0 and es[0, 1] != 0.0
 
 
 # --------------------------------------------------------------------------
