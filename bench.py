@@ -55,6 +55,11 @@ def parse():
     p.add_argument("--op-costs", type=int, nargs="+", default=[0, 16, 64, 256, 1024, 4096])
     p.add_argument("--op-cost-shape", type=int, nargs="+", default=[128, 128, 128])
     p.add_argument("--op-cost-box", type=int, nargs="+", default=[4, 4, 4])
+    p.add_argument("--no-corners", action="store_true",
+                   help="skip the corners-algorithm comparison (2-D)")
+    p.add_argument("--sweep-corners", action="store_true",
+                   help="box-complement vs the corners algorithm on 2-D tensors of several "
+                        "sizes and boxes: one JSON line per case")
     p.add_argument("--no-weak", action="store_true",
                    help="skip the weak excluded sums (total - included) for +")
     p.add_argument("--no-batched", action="store_true", help="skip the batched form")
@@ -189,6 +194,12 @@ def main():
         return
     if args.sweep_op_cost:
         sweep_op_cost(args, P, torch, np)
+        return
+    if args.sweep_corners:
+        for n in (1024, 4096, 8192, 16384):
+            for k in (4, 16, 64):
+                r = bench_corners(args, P, torch, np, (n, n), (k, k), ("sum", "max"))
+                print(json.dumps(r), flush=True)
         return
     from paper_2106_00124_amd import _lib
     from paper_2106_00124_amd.workloads import WORKLOADS
@@ -383,6 +394,8 @@ def main():
     del outs, ws
     torch.cuda.empty_cache()
     configs = None if args.no_configs else bench_configs(args, P, torch, np)
+    corners = None if args.no_corners else bench_corners(args, P, torch, np, (8192, 8192),
+                                                         (16, 16), ("sum", "max"))
     batched = None if args.no_batched else bench_batched(args, P, _lib, torch, np)
     served = None if args.no_served else bench_served(args, P, _lib, torch, np)
 
@@ -413,6 +426,7 @@ def main():
         "weak": weak,
         "min": mn,
         "configs": configs,
+        "corners": corners,
         "batched": batched,
         "served": served,
     }
@@ -674,6 +688,68 @@ def bench_configs(args, P, torch, np):
         res[name] = r
         del a, ws, outs
         torch.cuda.empty_cache()
+    return res
+
+
+def bench_corners(args, P, torch, np, shape, box, ops):
+    """Strong excluded sums of one 2-D fp32 tensor (N(0,1), seeded) by the
+    box-complement path (excluded output only) and by the corners algorithm,
+    the paper's comparison system: median event-timed call of each, the ratio,
+    and how far the two results are apart (max: bit-identical cells; +: the
+    largest difference over sqrt(sum A^2), the scale of the excluded sums)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    rng = np.random.default_rng(int(np.prod(shape)) + 31 * box[0] + box[1])
+    a_host = rng.standard_normal(shape).astype(np.float32)
+    a = torch.from_numpy(a_host).to(dev)
+    N = a.numel()
+    ws_bc = torch.empty(max(max(P.workspace_size(shape, box, torch.float32, op, "exc")
+                                for op in ops), 1), dtype=torch.uint8, device=dev)
+    ws_co = torch.empty(max(P.corners_workspace_size(shape, box, torch.float32), 1),
+                        dtype=torch.uint8, device=dev)
+    e_bc, e_co = torch.empty_like(a), torch.empty_like(a)
+    res = {"shape": list(shape), "box": list(box), "dtype": "f32", "output": "excluded",
+           "values": "N(0,1) numpy PCG64", "per_op": {},
+           "corners_workspace_bytes": ws_co.numel(), "box_complement_workspace_bytes":
+           ws_bc.numel()}
+
+    def timed(fn, reps):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ev = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            ev.append((e0, e1))
+        torch.cuda.synchronize()
+        return _pct([x.elapsed_time(y) for x, y in ev], 0.5)
+
+    scale = float(np.sqrt((a_host.astype(np.float64) ** 2).sum()))
+    for op in ops:
+        ms_bc = timed(lambda: P.run(a, box, op, "exc", exc_out=e_bc, workspace=ws_bc,
+                                    stream=stream), 20)
+        ms_co = timed(lambda: P.run_corners(a, box, op, exc_out=e_co, workspace=ws_co,
+                                            stream=stream), 20)
+        g, b = e_co.cpu().numpy(), e_bc.cpu().numpy()
+        if op == "sum":
+            agree = {"max_abs_diff_over_scale": float(np.max(np.abs(g.astype(np.float64) - b))
+                                                      / scale)}
+        else:
+            agree = {"identical_cells": int(np.count_nonzero(g == b)), "cells": int(g.size)}
+        res["per_op"][op] = {"box_complement_ms": round(ms_bc, 4),
+                             "corners_ms": round(ms_co, 4),
+                             "box_complement_gelem_per_s": round(N / (ms_bc * 1e-3) / 1e9, 2),
+                             "corners_gelem_per_s": round(N / (ms_co * 1e-3) / 1e9, 2),
+                             "corners_over_box_complement": round(ms_co / ms_bc, 3),
+                             "agreement": agree}
+        log(f"corners {shape} {box} {op}: box-complement {ms_bc:.4f} ms, corners {ms_co:.4f} ms "
+            f"({ms_co / ms_bc:.2f}x)")
+    del a, ws_bc, ws_co, e_bc, e_co
+    torch.cuda.empty_cache()
     return res
 
 

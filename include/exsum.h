@@ -180,6 +180,32 @@ exs_status exs_set_op_cost(int32_t cost);
 exs_status exs_op_probe(void *data_dev, int64_t n, int32_t reps, void *stream);
 
 /* ---------------------------------------------------------------------- */
+/* Corners algorithm: the paper's comparison system for strong excluded sums */
+/* ---------------------------------------------------------------------- */
+
+/* Strong excluded sums of a 2-D tensor by the corners algorithm (Sec. 1,
+ * "Corners Algorithm for Strong Excluded Sums"; App. A, "Analysis of Corners
+ * Algorithm"), kept beside exs_run to compare the two methods on the same
+ * device.  The complement of each box is cut into four disjoint regions,
+ * each holding one corner of the box and reaching the tensor's edges; each
+ * region's reduction is one entry of a full-tensor table (prefix or suffix
+ * along axis 0 of a prefix or suffix along axis 1), so no inverse is needed.
+ * Results equal exs_run's excluded output: bit-exact for integer + (wrapping),
+ * max and min; for f32/f64 + the same sums in another order.
+ *
+ * The job is as for exs_run with d == 2, mode == EXS_EXCLUDED, dtype EXS_F32,
+ * EXS_F64, EXS_I32 or EXS_I64 and any op; in_dev and exc_out_dev are
+ * C-contiguous n0 x n1 device tensors (caller-owned; exc_out_dev must not
+ * overlap in_dev).  The workspace (exs_corners_workspace_size: four n0 x n1
+ * tables plus six ceil(n0/64) x n1 arrays, 256-byte aligned, caller-owned)
+ * must not overlap either tensor.  Enqueued on `stream` without host
+ * synchronisation.  Errors: EXS_EINVAL for a malformed job or workspace,
+ * EXS_EUNSUPPORTED for d != 2 or (value, index) pairs, EXS_ENOMEM for a
+ * workspace smaller than needed, EXS_EDEVICE if a launch fails. */
+exs_status exs_corners_workspace_size(const exs_job *job, size_t *bytes);
+exs_status exs_run_corners(const exs_job *job, void *ws_dev, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------- */
 /* Input generation on the device (workload support, not part of the method) */
 /* ---------------------------------------------------------------------- */
 

@@ -101,6 +101,36 @@ def run(x, box, op="sum", mode="both", inc_out=None, exc_out=None, workspace=Non
     return (inc_out if m & _lib.INCLUDED else None, exc_out if m & _lib.EXCLUDED else None)
 
 
+def run_corners(x, box, op="sum", exc_out=None, workspace=None, stream=None):
+    """Strong excluded sums of the contiguous 2-D device tensor ``x`` by the
+    corners algorithm, the paper's comparison system (``exs_run_corners``):
+    the same results as ``run(x, box, op, "exc")``, by another method."""
+    import torch
+    if not x.is_cuda:
+        raise ExsError(1, "x must be a device tensor")
+    if not x.is_contiguous():
+        raise ExsError(1, "x must be contiguous")
+    if exc_out is None:
+        exc_out = torch.empty_like(x)
+    j = job_for(x, box, op, _lib.EXCLUDED, None, exc_out)
+    n = ctypes.c_size_t()
+    _lib.check(_lib.lib().exs_corners_workspace_size(ctypes.byref(j), ctypes.byref(n)))
+    if workspace is None or workspace.numel() < n.value:
+        workspace = torch.empty(max(n.value, 1), dtype=torch.uint8, device=x.device)
+    _lib.check(_lib.lib().exs_run_corners(ctypes.byref(j), ctypes.c_void_p(workspace.data_ptr()),
+                                          workspace.numel(), _stream_ptr(stream)))
+    return exc_out
+
+
+def corners_workspace_size(shape, box, dtype, op="sum") -> int:
+    """Workspace bytes ``run_corners`` needs (dtype: a torch dtype)."""
+    j = _lib.make_job(len(shape), _dtype_code(dtype), _OPS[op], _lib.EXCLUDED,
+                      list(shape), list(box), None, None, None)
+    n = ctypes.c_size_t()
+    _lib.check(_lib.lib().exs_corners_workspace_size(ctypes.byref(j), ctypes.byref(n)))
+    return n.value
+
+
 def pack_pairs(values, index=None):
     """(value, index) pairs as one int64 tensor of the values' shape: each
     element holds the float32 value's bits in its low half and the int32

@@ -49,6 +49,8 @@ SIGNATURES = {
     "exs_workspace_size": (ctypes.c_int, [_JP, ctypes.POINTER(ctypes.c_size_t)]),
     "exs_run": (ctypes.c_int, [_JP, _P, ctypes.c_size_t, _P]),
     "exs_run_noalloc": (ctypes.c_int, [_JP, _P]),
+    "exs_corners_workspace_size": (ctypes.c_int, [_JP, ctypes.POINTER(ctypes.c_size_t)]),
+    "exs_run_corners": (ctypes.c_int, [_JP, _P, ctypes.c_size_t, _P]),
     "exs_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "exs_last_error": (ctypes.c_char_p, []),
     "exs_version": (ctypes.c_char_p, []),

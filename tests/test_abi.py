@@ -163,3 +163,41 @@ def test_pair_dtype_validation():
                             None, 0x9000)
     h = ctypes.c_void_p()
     assert L.exs_batch_create(jobs, 1, None, ctypes.byref(h)) == _lib.EUNSUPPORTED
+
+
+def test_corners_validation_and_workspace():
+    """The corners entry points: d = 2 and EXS_EXCLUDED only, no pairs; the
+    workspace is four n0 x n1 tables and six ceil(n0/64) x n1 arrays, each
+    rounded up to 256 bytes (host only)."""
+    from paper_2106_00124_amd import _lib
+    L = _lib.lib()
+    n = ctypes.c_size_t()
+
+    def ws(d, dims, box, dtype=_lib.F32, op=_lib.SUM, mode=_lib.EXCLUDED):
+        j = _lib.make_job(d, dtype, op, mode, dims, box, None, None, None)
+        return L.exs_corners_workspace_size(ctypes.byref(j), ctypes.byref(n))
+
+    up = lambda b: (b + 255) // 256 * 256  # noqa: E731
+    for (n0, n1), es, dt in (((64, 64), 4, _lib.F32), ((130, 77), 8, _lib.I64),
+                             ((1, 1), 4, _lib.I32), ((1000, 3), 8, _lib.F64)):
+        for op in (_lib.SUM, _lib.MAX, _lib.MIN):
+            assert ws(2, [n0, n1], [1, 1], dt, op) == 0
+            S = (n0 + 63) // 64
+            assert n.value == 4 * up(n0 * n1 * es) + 6 * up(S * n1 * es)
+    assert ws(3, [4, 4, 4], [2, 2, 2]) == _lib.EUNSUPPORTED
+    assert ws(1, [8], [2]) == _lib.EUNSUPPORTED
+    assert ws(2, [8, 8], [2, 2], mode=_lib.INCLUDED) == _lib.EINVAL
+    assert ws(2, [8, 8], [2, 2], mode=_lib.INCLUDED | _lib.EXCLUDED) == _lib.EINVAL
+    assert ws(2, [8, 8], [2, 2], mode=_lib.EXCLUDED | _lib.WEAK) == _lib.EINVAL
+    assert ws(2, [8, 8], [9, 2]) == _lib.EINVAL
+    assert ws(2, [8, 8], [2, 2], dtype=_lib.VALIDX, op=_lib.MAX) == _lib.EUNSUPPORTED
+    # run: null pointers and a workspace over the input are refused on the host
+    j = _lib.make_job(2, _lib.F32, _lib.SUM, _lib.EXCLUDED, [8, 8], [2, 2], None, None, None)
+    assert L.exs_run_corners(ctypes.byref(j), None, 0, None) == _lib.EINVAL
+    j = _lib.make_job(2, _lib.F32, _lib.SUM, _lib.EXCLUDED, [8, 8], [2, 2], 0x10000, None,
+                      0x20000)
+    assert ws(2, [8, 8], [2, 2]) == 0
+    assert L.exs_run_corners(ctypes.byref(j), ctypes.c_void_p(0x10000), n.value,
+                             None) == _lib.EINVAL
+    assert L.exs_run_corners(ctypes.byref(j), ctypes.c_void_p(0x40000), 16,
+                             None) == _lib.ENOMEM
