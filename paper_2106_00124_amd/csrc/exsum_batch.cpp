@@ -88,9 +88,12 @@ struct ListSink {
             return;
         }
         const i64 rcb = I == 1 ? rows_blocks(O, n, k, ROWS_MIN_TASKS) : 0;
-        const bool rows_lds = I == 1 && O >= ROWS_PER_TASK && rows_tasks(O, n, k, rcb) >= ROWS_MIN_TASKS;
-        if (I == 1 && !rows_lds && narrow_ok(O * n, (int)sizeof(T), 32)) {
-            // rows of the contiguous axis, too few for the LDS-staged tasks:
+        const bool rows_lds = I == 1 && O >= rows_per_task(k) &&
+                              (kb > COOP_CS || rows_tasks(O, n, k, rcb) >= ROWS_MIN_TASKS);
+        if (I == 1 && !rows_lds && !(O < 64 && n > 256) &&
+            narrow_ok(O * n, (int)sizeof(T), 32)) {
+            // rows of the contiguous axis, too few for the LDS-staged tasks
+            // and not a few long ones (those go in chunks, as a strided axis):
             // one wavefront per task, segmented scans across the lanes
             s.kind = SK_BDBSV;
             s.cb = wave_rows_per_task(O);
@@ -105,12 +108,23 @@ struct ListSink {
             const i64 nbr = (n + k - 1) / k;
             s.cb = rcb;
             s.nchunks = (nbr + s.cb - 1) / s.cb;
-            s.ntasks = ((O + ROWS_PER_TASK - 1) / ROWS_PER_TASK) * s.nchunks;
+            s.ntasks = ((O + rows_per_task(k) - 1) / rows_per_task(k)) * s.nchunks;
+            push(s, kb);
+            return;
+        }
+        const i64 nb = (n + k - 1) / k, cols = O * I;
+        if (kb >= 32 && I > 1 && O * n * I * (i64)sizeof(T) < ((i64)1 << 31)) {
+            // boxes of 17 to 64 along a strided axis: lanes share a column
+            s.kind = SK_BDBSC;
+            const i64 C = 64 / coop_g(kb, (int)sizeof(T), false);
+            const i64 groups = (cols + C - 1) / C;
+            s.cb = coop_run_blocks(groups, nb);
+            s.nchunks = (nb + s.cb - 1) / s.cb;
+            s.ntasks = groups * s.nchunks * 64;
             push(s, kb);
             return;
         }
         s.kind = narrow_ok(O * n * I, (int)sizeof(T), kb) ? SK_BDBS : SK_BDBSW;
-        const i64 nb = (n + k - 1) / k, cols = O * I;
         i64 nch = (cfg.min_tasks + cols - 1) / cols;
         if (nch > nb) nch = nb;
         if (nch < 1) nch = 1;
@@ -191,7 +205,8 @@ struct ListSink {
             return;
         }
         Step s{};
-        s.kind = narrow_ok(n0 * M, (int)sizeof(T), kb) ? SK_AX0 : SK_AX0W;
+        const bool coop = kb >= 32 && n0 * M * (i64)sizeof(T) < ((i64)1 << 31);
+        s.kind = coop ? SK_AX0C : narrow_ok(n0 * M, (int)sizeof(T), kb) ? SK_AX0 : SK_AX0W;
         s.k = (int)k0;
         s.in0 = W;
         s.in1 = PX;
@@ -202,6 +217,16 @@ struct ListSink {
         s.n = n0;
         s.I = M;
         s.Q = Q;
+        if (coop) {
+            // boxes of 17 to 64 along axis 0: lanes share a point
+            const i64 C = 64 / coop_g(kb, (int)sizeof(T), true);
+            const i64 groups = (M + C - 1) / C;
+            s.cb = coop_run_blocks(groups, Q);
+            s.nchunks = (Q + s.cb - 1) / s.cb;
+            s.ntasks = groups * s.nchunks * 64;
+            push(s, kb);
+            return;
+        }
         i64 nseg = (cfg.min_tasks + M - 1) / M;
         if (nseg > Q) nseg = Q;
         if (nseg < 1) nseg = 1;
@@ -209,6 +234,13 @@ struct ListSink {
         s.nchunks = (Q + s.cb - 1) / s.cb;
         s.ntasks = M * s.nchunks;
         push(s, kb);
+    }
+    // blocks per run of a split-block step: runs enough for min_tasks threads
+    i64 coop_run_blocks(i64 groups, i64 nb) const {
+        i64 runs = (cfg.min_tasks + 64 * groups - 1) / (64 * groups);
+        if (runs > nb) runs = nb;
+        if (runs < 1) runs = 1;
+        return (nb + runs - 1) / runs;
     }
     void plane_axis0(const T*, const T*, const T*, const T*, T*, T*, i64, i64, i64, i64, i64, i64,
                      i64, i64) {}
@@ -332,7 +364,7 @@ static exs_status build(exs_batch* b, void* ws, const TuneCfg& cfg) {
                 for (i64 u = 0; u < (rows ? span : span / WL_CHUNK); ++u) table.push_back(local);
                 all.push_back(s);
                 if (rows)
-                    L.lds = std::max(L.lds, (size_t)ROWS_PER_TASK * rows_pitch(s.cb, s.k) *
+                    L.lds = std::max(L.lds, (size_t)rows_per_task(s.k) * rows_pitch(s.cb, s.k) *
                                                 dtype_size(L.dtype));
             }
             L.units = rows ? tb : tb / WL_CHUNK;

@@ -149,6 +149,15 @@ __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned voff) {
     else
         return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0));
 }
+// The same with a uniform part of the offset in a scalar register (soff).
+template <typename T>
+__device__ __forceinline__ T bload_s(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte elements");
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
 template <typename T>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, T v) {
     static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte elements");

@@ -44,6 +44,42 @@ __global__ __launch_bounds__(256) void k_bdbs_wave(const T* __restrict__ in, T* 
     if (task < ntasks) task_bdbs_wave<T, Op>(in, out, O, n, k, rpt, task);
 }
 
+// Split-block forms for boxes of 17 to 64 (coop_g lanes per column): one
+// wavefront per task.
+template <typename T, class Op, int KB>
+__global__ __launch_bounds__(256) void k_bdbs_coop(const T* __restrict__ in, T* __restrict__ out,
+                                                   i64 O, i64 n, i64 I, int k, i64 cb,
+                                                   i64 ntasks) {
+    const i64 task = ((i64)blockIdx.x * 256 + threadIdx.x) >> 6;
+    if (task < ntasks) task_bdbs_coop<T, Op, KB>(in, out, O, n, I, k, cb, task);
+}
+
+template <typename T, class Op, int KB>
+__global__ __launch_bounds__(256) void k_axis0_coop(const T* __restrict__ W,
+                                                    const T* __restrict__ PX,
+                                                    const T* __restrict__ SX,
+                                                    const T* __restrict__ Trest,
+                                                    T* __restrict__ exc, T* __restrict__ inc,
+                                                    i64 n0, i64 M, int k0, i64 Q, i64 segblocks,
+                                                    i64 ntasks) {
+    const i64 task = ((i64)blockIdx.x * 256 + threadIdx.x) >> 6;
+    if (task < ntasks)
+        task_axis0_coop<T, Op, KB>(W, PX, SX, Trest, exc, inc, n0, M, k0, Q, segblocks, task);
+}
+
+// Wavefront tasks of the split-block kernels: enough runs along the axis that
+// the launch has about 4096 wavefronts; returns the blocks per run and sets
+// the task count.
+static inline i64 coop_runs(i64 groups, i64 nb, i64* ntasks) {
+    i64 runs = (4096 + groups - 1) / groups;
+    if (runs > nb) runs = nb;
+    if (runs < 1) runs = 1;
+    const i64 per = (nb + runs - 1) / runs;
+    runs = (nb + per - 1) / per;
+    *ntasks = groups * runs;
+    return per;
+}
+
 template <typename T, class Op, int KB>
 __global__ __launch_bounds__(64) void k_bdbs_rows(const T* __restrict__ in, T* __restrict__ out,
                                                   i64 O, i64 n, int k, i64 cb, i64 nchunks) {
@@ -418,16 +454,24 @@ static inline unsigned grid_for(i64 threads, int block = 256) {
 template <typename T, class Op>
 void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st) {
     const int kb = bucket_for(k);
-    KTimer timer(kb == 0 ? "k_bdbs_2sweep" : "k_bdbs", st);
     if (kb == 0) {
+        KTimer timer("k_bdbs_2sweep", st);
         hipLaunchKernelGGL((k_bdbs_2sweep<T, Op>), dim3(grid_for(O * I)), dim3(256), 0, st,
                            in, out, O, n, I, k);
         return;
     }
     const i64 nb = (n + k - 1) / k;
     const i64 rcb = I == 1 ? rows_blocks(O, n, k, ROWS_MIN_TASKS) : 0;
-    const bool rows_lds = I == 1 && O >= ROWS_PER_TASK && rows_tasks(O, n, k, rcb) >= ROWS_MIN_TASKS;
-    if (I == 1 && !rows_lds && narrow_ok(O * n, (int)sizeof(T), 32)) {
+    // (boxes over 16: always, the wavefront kernel walks whole rows)
+    const bool rows_lds = I == 1 && O >= rows_per_task(k) &&
+                          (kb > COOP_CS || rows_tasks(O, n, k, rcb) >= ROWS_MIN_TASKS);
+    // a few long rows: chunks of the rows in parallel (the generic tasks)
+    // rather than one wavefront walking each row from end to end
+    const bool wave = I == 1 && !rows_lds && !(O < 64 && n > 256) &&
+                      narrow_ok(O * n, (int)sizeof(T), 32);
+    KTimer timer(I > 1 ? (kb >= 32 ? "k_bdbs_coop" : "k_bdbs")
+                       : wave ? "k_bdbs_wave" : "k_bdbs_rows", st);
+    if (wave) {
         // rows of the contiguous axis, too few for the LDS-staged tasks: one
         // wavefront per task (lanes along the row, coalesced)
         const i64 rpt = wave_rows_per_task(O);
@@ -444,7 +488,7 @@ void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st
         const i64 cb = rcb;
         const i64 nch = (nb + cb - 1) / cb;
         const i64 tasks = rows_tasks(O, n, k, cb);
-        const size_t lds = (size_t)ROWS_PER_TASK * rows_pitch(cb, k) * sizeof(T);
+        const size_t lds = (size_t)rows_per_task(k) * rows_pitch(cb, k) * sizeof(T);
 #define EXS_ROWS_CASE(KB)                                                                     \
     case KB:                                                                                  \
         hipLaunchKernelGGL((k_bdbs_rows<T, Op, KB>), dim3((unsigned)tasks), dim3(64), lds, st, \
@@ -458,6 +502,19 @@ void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st
         return;
     }
     const i64 cols = O * I;
+    if (kb >= 32 && I > 1 && O * n * I * (i64)sizeof(T) < ((i64)1 << 31)) {
+        // boxes of 17 to 64 along a strided axis: lanes share a column
+        i64 tasks = 0;
+        const i64 C = 64 / coop_g(kb, (int)sizeof(T), false);
+        const i64 cb = coop_runs((cols + C - 1) / C, nb, &tasks);
+        if (kb == 32)
+            hipLaunchKernelGGL((k_bdbs_coop<T, Op, 32>), dim3(grid_for(tasks * 64)), dim3(256), 0,
+                               st, in, out, O, n, I, (int)k, cb, tasks);
+        else
+            hipLaunchKernelGGL((k_bdbs_coop<T, Op, 64>), dim3(grid_for(tasks * 64)), dim3(256), 0,
+                               st, in, out, O, n, I, (int)k, cb, tasks);
+        return;
+    }
     i64 nchunks = (65536 + cols - 1) / cols;
     if (nchunks > nb) nchunks = nb;
     if (nchunks < 1) nchunks = 1;
@@ -700,6 +757,22 @@ void launch_axis0(const T* W, const T* PX, const T* SX, const T* Trest, T* exc, 
             hipLaunchKernelGGL((k_ex1d_2sweep<T, Op>), dim3(grid_for(M)), dim3(256), 0, st, W,
                                Trest, exc, n0, M, k0);
         if (inc) launch_bdbs<T, Op>(W, inc, 1, n0, M, k0, st);
+        return;
+    }
+    if (kb >= 32 && n0 * M * (i64)sizeof(T) < ((i64)1 << 31)) {
+        // boxes of 17 to 64 along axis 0: lanes share a point
+        i64 tasks = 0;
+        const i64 C = 64 / coop_g(kb, (int)sizeof(T), true);
+        const i64 segblocks = coop_runs((M + C - 1) / C, Q, &tasks);
+        KTimer timer("k_axis0_coop", st);
+        if (kb == 32)
+            hipLaunchKernelGGL((k_axis0_coop<T, Op, 32>), dim3(grid_for(tasks * 64)), dim3(256), 0,
+                               st, W, PX, SX, Trest, exc, inc, n0, M, (int)k0, Q, segblocks,
+                               tasks);
+        else
+            hipLaunchKernelGGL((k_axis0_coop<T, Op, 64>), dim3(grid_for(tasks * 64)), dim3(256), 0,
+                               st, W, PX, SX, Trest, exc, inc, n0, M, (int)k0, Q, segblocks,
+                               tasks);
         return;
     }
     i64 nseg = (65536 + M - 1) / M;

@@ -98,15 +98,16 @@ static const T* filter_axes(const T* src, const i64* n, const i64* k, int d, int
 }
 
 // Block scans of a level (PX, SX over the Q blocks of each of the M points,
-// and R = op of Ga over all blocks).  With few points and many blocks the
-// direct scan is a long serial walk per point; then the blocks are cut into
-// segments of L, the segment totals are scanned the same way (recursively),
-// and the segments are expanded in parallel.
+// and R = op of Ga over all blocks).  The direct scan is one serial walk over
+// the Q blocks per point; unless the points alone fill the GPU (2^18 threads)
+// or the walk is short, the blocks are cut into segments of L, the segment
+// totals are scanned the same way (recursively), and the segments are
+// expanded in parallel.
 template <typename T, class Sink>
 static void emit_blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M, Arena& ar,
                            bool dry, Sink& sink) {
     constexpr i64 L = 64;
-    if (M >= 16384 || Q <= L) {
+    if (M >= ((i64)1 << 18) || Q <= L) {
         if (!dry) sink.blockscan(Gw, Ga, PX, SX, R, Q, M);
         return;
     }

@@ -28,7 +28,10 @@ enum StepKind : int {
     SK_AX0W = 10,  // SK_AX0 for tensors of 2^31 bytes or more (64-bit addressing)
     SK_BDBSV = 11, // BDBS along the contiguous axis, one wavefront per task (k <= 64,
                    // tensors below 2^31 bytes); its task count is in threads
-    SK_NKINDS = 12
+    SK_BDBSC = 12, // BDBS along a strided axis, boxes of 17 to 64 split over 2 or 4
+                   // lanes per column (tensors below 2^31 bytes); count in threads
+    SK_AX0C = 13,  // SK_AX0 the same way (boxes of 17 to 64 along axis 0)
+    SK_NKINDS = 14
 };
 
 // One step of the generic path.  Pointers are device pointers; the meaning
@@ -367,15 +370,86 @@ __device__ __forceinline__ void task_ex2(const T* __restrict__ W, const T* __res
     }
 }
 
+// ---------------------------------------------------------------------------
+// Split-block tasks for boxes longer than 16 along a strided axis and along
+// axis 0.  A thread that holds a whole block (and the next) needs two
+// registers per slot of the bucket, which at 32 or 64 slots leaves one to
+// four wavefronts per SIMD and starves the memory pipeline.  Here G lanes
+// share one column, each holding CS consecutive slots of a block: the range
+// prefixes and suffixes of the block (Sec. 3) are each lane's own scans over
+// its slots combined with the op of the other lanes' segment totals before or
+// after it.  A wavefront covers C = 64 / G columns: lanes g * C .. g * C + C - 1
+// hold segment g of the C columns, so one load reads C consecutive elements
+// in each of G rows.  Slots past the box length or the tensor end are the
+// identity; their loads read nothing and their stores land nowhere.  32-bit
+// byte offsets: tensors below 2^31 bytes.  From global memory G = 2 where the
+// registers allow (rows of 32 elements per load: 128 bytes of 4-byte
+// elements), else 4; CS = KB / G.
+// ---------------------------------------------------------------------------
+constexpr int COOP_CS = 16;  // slots per lane of the LDS-staged row tasks
+
+// lanes per column of the global-memory split-block tasks: 2, or 4 where 32
+// slots per lane would spill past half the register file (the axis-0 stream,
+// which holds two blocks and a scan, and 8-byte elements) at KB = 64
+__host__ __device__ constexpr int coop_g(int kb, int es, bool axis0) {
+    return (kb == 64 && (axis0 || es == 8)) ? 4 : 2;
+}
+
+// ADJ: the G lanes of a column are adjacent (lane = c * G + g) -- for
+// operands staged in LDS, where no load coalescing is at stake.
+template <typename T, class Op, int G, bool ADJ = false>
+struct CoopLanes {
+    static constexpr int C = 64 / G;
+    int c, g;  // column within the wavefront's group, segment of the block
+    __device__ __forceinline__ explicit CoopLanes(int lane)
+        : c(ADJ ? lane / G : lane % C), g(ADJ ? lane % G : lane / C) {}
+    // op of the segment totals of this lane's column before and after its
+    // own segment (every lane of the wavefront takes part)
+    __device__ __forceinline__ void scan(T tot, T& before, T& after) const {
+        const T e = Op::template id<T>();
+        before = e;
+        after = e;
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const T t = G == 1 ? tot : wshfl(tot, ADJ ? c * G + j : c + j * C);
+            if (j < g) before = Op::apply(before, t);
+            if (j > g) after = Op::apply(after, t);
+        }
+    }
+};
+
+// Load this lane's slots of one block: `lim` = slots of the segment inside
+// the box and the tensor (<= 0: none), `ob` = byte offset of its first slot,
+// the slot's row in the scalar offset.  A slot past `lim` still issues its
+// load -- of an element of this tensor, or past the descriptor's range, which
+// reads 0 -- and takes the identity instead of what it read.
+template <typename T, class Op, int CS>
+__device__ __forceinline__ void coop_load(__amdgpu_buffer_rsrc_t r, unsigned ob, unsigned rowb,
+                                          int lim, T (&v)[CS]) {
+    const T e = Op::template id<T>();
+#pragma unroll
+    for (int s = 0; s < CS; ++s) {
+        const T t = bload_s<T>(r, ob, (unsigned)s * rowb);
+        v[s] = s < lim ? t : e;
+    }
+}
+
 // BDBS along the contiguous axis (rows of n elements, I == 1).  Lanes that
 // each walk their own row would touch 64 rows per load; instead one wavefront
 // (a workgroup of 64 threads) owns 64 rows and a run of cb blocks: the tile,
 // with the k - 1 columns of the next block, is staged in LDS by coalesced row
 // loads, each lane box-sums its row from LDS (block suffixes in registers, as
 // in bdbs_row), writes the results in place, and the tile leaves by coalesced
-// row stores.  LDS: 64 x rows_pitch(cb, k) elements (odd pitch: no bank
-// conflicts between lanes reading their rows).
-constexpr int ROWS_PER_TASK = 64;
+// row stores.  For boxes over 16 a task owns 64 / G rows and G lanes share a
+// row (COOP_CS slots of each block per lane, as in the split-block tasks).
+// LDS: rows x rows_pitch(cb, k) elements (odd pitch: few bank conflicts
+// between lanes reading their rows).
+// Rows per task: 64, or 64 / G for boxes of 17 to 64 (G lanes per row, one
+// pass over the tile; the smaller tile leaves room in LDS for more tasks).
+__host__ __device__ constexpr int rows_per_task_kb(int kb) {
+    return kb > COOP_CS ? 64 / (kb / COOP_CS) : 64;
+}
+inline int rows_per_task(i64 k) { return rows_per_task_kb(bucket_for(k)); }
 __host__ __device__ inline int rows_pitch(i64 cb, i64 k) { return (int)((cb * k + k - 1) | 1); }
 
 // Row tasks pay off once they fill the GPU (four wavefronts per CU).
@@ -383,7 +457,8 @@ constexpr i64 ROWS_MIN_TASKS = 1024;
 
 inline i64 rows_tasks(i64 O, i64 n, i64 k, i64 cb) {
     const i64 nb = (n + k - 1) / k;
-    return ((O + ROWS_PER_TASK - 1) / ROWS_PER_TASK) * ((nb + cb - 1) / cb);
+    const i64 rpt = rows_per_task(k);
+    return ((O + rpt - 1) / rpt) * ((nb + cb - 1) / cb);
 }
 
 // Blocks per row task: at most 64 columns, fewer while there are fewer than
@@ -392,7 +467,7 @@ inline i64 rows_blocks(i64 O, i64 n, i64 k, i64 min_tasks) {
     const i64 nb = (n + k - 1) / k;
     i64 cb = 64 / k > 1 ? 64 / k : 1;
     if (cb > nb) cb = nb;
-    const i64 groups = (O + ROWS_PER_TASK - 1) / ROWS_PER_TASK;
+    const i64 groups = (O + rows_per_task(k) - 1) / rows_per_task(k);
     while (cb > 1 && groups * ((nb + cb - 1) / cb) < min_tasks) cb = (cb + 1) / 2;
     return cb;
 }
@@ -412,13 +487,14 @@ __device__ __forceinline__ void task_bdbs_rows(const T* __restrict__ in, T* __re
     const i64 rin = (b1 - b0) * k + k - 1, rout = (b1 - b0) * k;
     const int win = (int)(rin < n - col0 ? rin : n - col0);
     const int wout = (int)(rout < n - col0 ? rout : n - col0);
-    const i64 row0 = g * ROWS_PER_TASK;
+    constexpr int RPT = rows_per_task_kb(KB);
+    const i64 row0 = g * RPT;
     // stage the tile (identity past the row end and in the unused pitch);
     // LW <= 127, so two 64-column passes cover a row.  Loads are issued in
     // batches of RB rows before any of them is written to LDS.
-    constexpr int RB = 32;
+    constexpr int RB = RPT < 32 ? RPT : 32;
 #pragma unroll
-    for (int r0 = 0; r0 < ROWS_PER_TASK; r0 += RB) {
+    for (int r0 = 0; r0 < RPT; r0 += RB) {
         T v[RB][2];
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) {
@@ -439,39 +515,92 @@ __device__ __forceinline__ void task_bdbs_rows(const T* __restrict__ in, T* __re
         }
     }
     __syncthreads();
-    T* my = lds + lane * LW;
-    T cur[KB], nxt[KB];
+    if constexpr (KB > COOP_CS) {
+        // boxes of 17 to 64: G adjacent lanes per row (the task's 64 / G
+        // rows), COOP_CS slots of each block per lane
+        constexpr int G = KB / COOP_CS, CS = COOP_CS;
+        static_assert(RPT * G == 64, "one pass over the tile");
+        const CoopLanes<T, Op, G, true> ln(lane);
+        const int s0 = ln.g * CS;
+        {
+            T* my = lds + ln.c * LW;
+            T rs[CS], v[CS];
 #pragma unroll
-    for (int r = 0; r < KB; ++r) cur[r] = r < k ? my[r] : e;
-    {
-        T s = e;
+            for (int s = 0; s < CS; ++s) v[s] = s0 + s < k ? my[s0 + s] : e;
+            {
+                T tot = e;
 #pragma unroll
-        for (int r = KB - 1; r >= 0; --r) {
-            if (r < k) { s = Op::apply(cur[r], s); cur[r] = s; }
-        }
-    }
-    for (i64 b = b0; b < b1; ++b) {
-        const int base = (int)(b - b0) * k;
+                for (int s = 0; s < CS; ++s) tot = Op::apply(tot, v[s]);
+                T before, after;
+                ln.scan(tot, before, after);
+                T sf = after;
 #pragma unroll
-        for (int r = 0; r < KB; ++r) nxt[r] = (r < k && base + k + r < LW) ? my[base + k + r] : e;
-        T p = e;
+                for (int s = CS - 1; s >= 0; --s) {
+                    sf = Op::apply(v[s], sf);
+                    rs[s] = sf;
+                }
+            }
+            for (i64 b = b0; b < b1; ++b) {
+                const int base = (int)(b - b0) * k;
 #pragma unroll
-        for (int r = 0; r < KB; ++r) {
-            if (r < k) {
-                T v = cur[r];
-                if (r > 0) { p = Op::apply(p, nxt[r - 1]); v = Op::apply(v, p); }
-                my[base + r] = v;
+                for (int s = 0; s < CS; ++s) {
+                    const int x = base + k + s0 + s;
+                    v[s] = (s0 + s < k && x < LW) ? my[x] : e;
+                }
+                T tot = e;
+#pragma unroll
+                for (int s = 0; s < CS; ++s) tot = Op::apply(tot, v[s]);
+                T before, after;
+                ln.scan(tot, before, after);
+                T p = before;
+#pragma unroll
+                for (int s = 0; s < CS; ++s) {
+                    if (s0 + s < k) my[base + s0 + s] = Op::apply(rs[s], p);
+                    p = Op::apply(p, v[s]);
+                }
+                T sf = after;
+#pragma unroll
+                for (int s = CS - 1; s >= 0; --s) {
+                    sf = Op::apply(v[s], sf);
+                    rs[s] = sf;
+                }
             }
         }
-        T s = e;
+    } else {
+        T* my = lds + lane * LW;
+        T cur[KB], nxt[KB];
 #pragma unroll
-        for (int r = KB - 1; r >= 0; --r) {
-            if (r < k) { s = Op::apply(nxt[r], s); cur[r] = s; }
+        for (int r = 0; r < KB; ++r) cur[r] = r < k ? my[r] : e;
+        {
+            T s = e;
+#pragma unroll
+            for (int r = KB - 1; r >= 0; --r) {
+                if (r < k) { s = Op::apply(cur[r], s); cur[r] = s; }
+            }
+        }
+        for (i64 b = b0; b < b1; ++b) {
+            const int base = (int)(b - b0) * k;
+#pragma unroll
+            for (int r = 0; r < KB; ++r) nxt[r] = (r < k && base + k + r < LW) ? my[base + k + r] : e;
+            T p = e;
+#pragma unroll
+            for (int r = 0; r < KB; ++r) {
+                if (r < k) {
+                    T v = cur[r];
+                    if (r > 0) { p = Op::apply(p, nxt[r - 1]); v = Op::apply(v, p); }
+                    my[base + r] = v;
+                }
+            }
+            T s = e;
+#pragma unroll
+            for (int r = KB - 1; r >= 0; --r) {
+                if (r < k) { s = Op::apply(nxt[r], s); cur[r] = s; }
+            }
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int r0 = 0; r0 < ROWS_PER_TASK; r0 += RB) {
+    for (int r0 = 0; r0 < RPT; r0 += RB) {
         T v[RB][2];
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) {
@@ -594,6 +723,185 @@ __device__ __forceinline__ void task_bdbs_wave(const T* __restrict__ in, T* __re
     }
 }
 
+// BDBS along the middle axis of an (O, n, I) tensor (I >= 1): task = (run of
+// `cb` blocks, group of C columns), the group fastest; one wavefront each.
+template <typename T, class Op, int KB>
+__device__ __forceinline__ void task_bdbs_coop(const T* __restrict__ in, T* __restrict__ out,
+                                               i64 O, i64 n_, i64 I_, int k, i64 cb, i64 task) {
+    constexpr int G = coop_g(KB, sizeof(T), false), CS = KB / G;
+    using L = CoopLanes<T, Op, G>;
+    constexpr int C = L::C;
+    const L ln(threadIdx.x & 63);
+    const T e = Op::template id<T>();
+    const i64 cols = O * I_;
+    const i64 ngroups = (cols + C - 1) / C;
+    const i64 grp = task % ngroups, run = task / ngroups;
+    const int n = (int)n_;
+    const int nb = (n + k - 1) / k;
+    const int b0 = (int)(run * cb);
+    if (b0 >= nb) return;  // the whole wavefront
+    const int b1 = b0 + (int)cb < nb ? b0 + (int)cb : nb;
+    const i64 col = grp * C + ln.c;
+    const bool live = col < cols;
+    constexpr unsigned es = sizeof(T);
+    const unsigned bytes = (unsigned)(cols * n_ * (i64)es);
+    const __amdgpu_buffer_rsrc_t rin = buf(in, bytes), rout = buf(out, bytes);
+    const unsigned rowb = (unsigned)(I_ * (i64)es);
+    const i64 o = live ? col / I_ : 0, i = live ? col % I_ : 0;
+    // byte offset of slot 0 of this lane's segment in block 0
+    const unsigned base = (unsigned)((o * n_ * I_ + i) * (i64)es) + (unsigned)(ln.g * CS) * rowb;
+    auto lim_of = [&](int b) { return live ? min(k, n - b * k) - ln.g * CS : 0; };
+
+    T rs[CS], v[CS];
+    coop_load<T, Op, CS>(rin, base + (unsigned)(b0 * k) * rowb, rowb, lim_of(b0), v);
+    {
+        T tot = e;
+#pragma unroll
+        for (int s = 0; s < CS; ++s) tot = Op::apply(tot, v[s]);
+        T before, after;
+        ln.scan(tot, before, after);
+        T sf = after;
+#pragma unroll
+        for (int s = CS - 1; s >= 0; --s) {
+            sf = Op::apply(v[s], sf);
+            rs[s] = sf;
+        }
+    }
+    for (int b = b0; b < b1; ++b) {
+        const int limn = b + 1 < nb ? lim_of(b + 1) : 0;
+        coop_load<T, Op, CS>(rin, base + (unsigned)((b + 1) * k) * rowb, rowb, limn, v);
+        T tot = e;
+#pragma unroll
+        for (int s = 0; s < CS; ++s) tot = Op::apply(tot, v[s]);
+        T before, after;
+        ln.scan(tot, before, after);
+        // block b: range suffix op range prefix of block b + 1 before the slot
+        const int limc = lim_of(b);
+        const unsigned oc = base + (unsigned)(b * k) * rowb;
+        T p = before;
+#pragma unroll
+        for (int s = 0; s < CS; ++s) {
+            bstore<T>(rout, s < limc ? oc + (unsigned)s * rowb : NOWHERE, Op::apply(rs[s], p));
+            p = Op::apply(p, v[s]);
+        }
+        T sf = after;
+#pragma unroll
+        for (int s = CS - 1; s >= 0; --s) {
+            sf = Op::apply(v[s], sf);
+            rs[s] = sf;
+        }
+    }
+}
+
+// The axis-0 stream of an (n0, M) tensor W (box-summed over the other axes):
+// excluded sums (the op of everything before the row, the rows from the same
+// row of the next block on, and SX beyond that; Trest folded into the
+// running prefix) and included sums (BDBS along axis 0).  Task = (run of
+// `segblocks` blocks, group of C points), the group fastest.
+template <typename T, class Op, int KB>
+__device__ __forceinline__ void task_axis0_coop(const T* __restrict__ W, const T* __restrict__ PX,
+                                                const T* __restrict__ SX,
+                                                const T* __restrict__ Trest,
+                                                T* __restrict__ exc, T* __restrict__ inc,
+                                                i64 n0_, i64 M_, int k0, i64 Q_, i64 segblocks,
+                                                i64 task) {
+    constexpr int G = coop_g(KB, sizeof(T), true), CS = KB / G;
+    using L = CoopLanes<T, Op, G>;
+    constexpr int C = L::C;
+    const L ln(threadIdx.x & 63);
+    const T e = Op::template id<T>();
+    const int n0 = (int)n0_, Q = (int)Q_;
+    const i64 ngroups = (M_ + C - 1) / C;
+    const i64 grp = task % ngroups, run = task / ngroups;
+    const int qa = (int)(run * segblocks);
+    if (qa >= Q) return;  // the whole wavefront
+    const int qb = qa + (int)segblocks < Q ? qa + (int)segblocks : Q;
+    const i64 m = grp * C + ln.c;
+    const bool live = m < M_;
+    const bool do_ex = exc != nullptr, do_inc = inc != nullptr;
+    constexpr unsigned es = sizeof(T);
+    const unsigned rowb = (unsigned)(M_ * (i64)es);
+    const unsigned nbytes = (unsigned)n0 * rowb;
+    const unsigned qbytes = (unsigned)Q * rowb;
+    const __amdgpu_buffer_rsrc_t rw = buf(W, nbytes);
+    const __amdgpu_buffer_rsrc_t rex = buf(exc, do_ex ? nbytes : 0u);
+    const __amdgpu_buffer_rsrc_t rin = buf(inc, do_inc ? nbytes : 0u);
+    const __amdgpu_buffer_rsrc_t rsx = buf(SX, do_ex ? qbytes : 0u);
+    const unsigned mo = live ? (unsigned)(m * (i64)es) : 0u;
+    const unsigned base = mo + (unsigned)(ln.g * CS) * rowb;
+    auto lim_of = [&](int q) { return live ? min(k0, n0 - q * k0) - ln.g * CS : 0; };
+
+    // w: raw values of the held block q; wb, wa: op of its other segments
+    // before / after this lane's; wt: op of the whole block
+    T w[CS], v[CS], t[CS];
+    T wb, wa, wt;
+    coop_load<T, Op, CS>(rw, base + (unsigned)(qa * k0) * rowb, rowb, lim_of(qa), w);
+    {
+        T tot = e;
+#pragma unroll
+        for (int s = 0; s < CS; ++s) tot = Op::apply(tot, w[s]);
+        ln.scan(tot, wb, wa);
+        wt = Op::apply(Op::apply(wb, tot), wa);
+    }
+    // Pb: op of every row before the held block, with the lower-dimensional term
+    T Pb = e;
+    if (do_ex) {
+        Pb = bload<T>(buf(PX, qbytes), mo + (unsigned)qa * rowb);
+        if (Trest) Pb = Op::apply(Pb, bload<T>(buf(Trest, rowb), mo));
+        if (!live) Pb = e;
+    }
+    for (int q = qa; q < qb; ++q) {
+        const int limn = q + 1 < Q ? lim_of(q + 1) : 0;
+        coop_load<T, Op, CS>(rw, base + (unsigned)((q + 1) * k0) * rowb, rowb, limn, v);
+        T vt = e;
+#pragma unroll
+        for (int s = 0; s < CS; ++s) vt = Op::apply(vt, v[s]);
+        T vb, va;
+        ln.scan(vt, vb, va);
+        const int limc = lim_of(q);
+        const unsigned oc = base + (unsigned)(q * k0) * rowb;
+        if (do_inc) {
+            // range suffix of block q from the slot on, op range prefix of
+            // block q + 1 before the slot
+            T p = vb;
+#pragma unroll
+            for (int s = 0; s < CS; ++s) {
+                t[s] = p;
+                p = Op::apply(p, v[s]);
+            }
+            T sf = wa;
+#pragma unroll
+            for (int s = CS - 1; s >= 0; --s) {
+                sf = Op::apply(w[s], sf);
+                bstore<T>(rin, s < limc ? oc + (unsigned)s * rowb : NOWHERE, Op::apply(sf, t[s]));
+            }
+        }
+        if (do_ex) {
+            // everything before the row, then the rows of block q + 1 from the
+            // same slot on and the blocks after it
+            T p = Op::apply(Pb, wb);
+#pragma unroll
+            for (int s = 0; s < CS; ++s) {
+                t[s] = p;
+                p = Op::apply(p, w[s]);
+            }
+            const T sxv = bload<T>(rsx, mo + (unsigned)(q + 1) * rowb);
+            T sf = Op::apply(va, (q + 1 < Q && live) ? sxv : e);
+#pragma unroll
+            for (int s = CS - 1; s >= 0; --s) {
+                sf = Op::apply(v[s], sf);
+                bstore<T>(rex, s < limc ? oc + (unsigned)s * rowb : NOWHERE, Op::apply(t[s], sf));
+            }
+            Pb = Op::apply(Pb, wt);
+        }
+#pragma unroll
+        for (int s = 0; s < CS; ++s) w[s] = v[s];
+        wb = vb;
+        wa = va;
+        wt = Op::apply(Op::apply(vb, vt), va);
+    }
+}
+
 // Dispatch one task of a recorded step (KB: the register bucket of the step,
 // for the kinds that have one).
 template <typename T, class Op, int KIND, int KB>
@@ -616,6 +924,13 @@ __device__ __forceinline__ void run_task(const Step& s, i64 i) {
                            (T*)s.out1, s.Q, s.I, s.cb, i);
     else if constexpr (KIND == SK_BDBSV)
         task_bdbs_wave<T, Op>((const T*)s.in0, (T*)s.out0, s.O, s.n, s.k, s.cb, i >> 6);
+    else if constexpr (KIND == SK_BDBSC)
+        task_bdbs_coop<T, Op, KB>((const T*)s.in0, (T*)s.out0, s.O, s.n, s.I, s.k, s.cb,
+                                  i >> 6);
+    else if constexpr (KIND == SK_AX0C)
+        task_axis0_coop<T, Op, KB>(
+            (const T*)s.in0, (const T*)s.in1, (const T*)s.in2, (const T*)s.in3, (T*)s.out0,
+            (T*)s.out1, s.n, s.I, s.k, s.Q, s.cb, i >> 6);
     else if constexpr (KIND == SK_AX0 || KIND == SK_AX0W)
         task_axis0<T, Op, KB, KIND == SK_AX0>((const T*)s.in0, (const T*)s.in1, (const T*)s.in2,
                                               (const T*)s.in3, (T*)s.out0, (T*)s.out1, s.n, s.I,

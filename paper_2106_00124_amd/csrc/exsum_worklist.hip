@@ -68,6 +68,10 @@ static void launch_kb(int kb, const Step* steps, const int* table, i64 nchunks, 
         switch (kb) {
             EXS_WL(1) EXS_WL(2) EXS_WL(4) EXS_WL(8) EXS_WL(16) EXS_WL(32) EXS_WL(64)
         }
+    } else if constexpr (KIND == SK_BDBSC || KIND == SK_AX0C) {
+        switch (kb) {
+            EXS_WL(32) EXS_WL(64)
+        }
     } else {
         hipLaunchKernelGGL((k_worklist<T, Op, KIND, 1>), dim3(grid), dim3(256), 0, st, steps,
                            table, nchunks);
@@ -91,6 +95,8 @@ static void launch_kind(int kind, int kb, const Step* steps, const int* table, i
         case SK_BDBSW: launch_kb<T, Op, SK_BDBSW>(kb, steps, table, units, grid, st); break;
         case SK_AX0W: launch_kb<T, Op, SK_AX0W>(kb, steps, table, units, grid, st); break;
         case SK_BDBSV: launch_kb<T, Op, SK_BDBSV>(kb, steps, table, units, grid, st); break;
+        case SK_BDBSC: launch_kb<T, Op, SK_BDBSC>(kb, steps, table, units, grid, st); break;
+        case SK_AX0C: launch_kb<T, Op, SK_AX0C>(kb, steps, table, units, grid, st); break;
     }
 }
 

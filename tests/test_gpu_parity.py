@@ -64,6 +64,23 @@ CASES = [
     # enough rows along the contiguous axis for the LDS-staged row kernel
     ((65536, 130), (3, 5)),
     ((256, 64, 200), (2, 3, 64)),
+    # boxes of 17 to 64 along strided axes and axis 0 (2 or 4 lanes per
+    # column): fewer columns than a wavefront's group (columns of several
+    # outer indices in one group), ragged groups, k = n, many runs along a
+    # long axis with few columns, lower levels adding their terms
+    ((200, 47, 3), (1, 40, 1)),
+    ((90, 33), (17, 1)),
+    ((3000, 5), (64, 2)),
+    ((64, 100, 16), (3, 33, 2)),
+    ((50, 129, 40), (20, 64, 3)),
+    ((2, 2000, 70), (2, 37, 5)),
+    ((100, 48), (48, 48)),
+    ((65, 64, 64), (64, 17, 32)),
+    ((33, 20, 30, 40), (33, 20, 18, 3)),
+    # ... and along the contiguous axis of many rows (LDS-staged tiles of
+    # 64 / G rows)
+    ((20000, 70), (2, 33)),
+    ((8192, 100), (3, 20)),
 ]
 
 DTYPE_OPS = [("f32", "sum"), ("f32", "max"), ("f32", "min"), ("f64", "sum"), ("f64", "max"),
