@@ -88,13 +88,13 @@ struct ListSink {
             return;
         }
         const i64 rcb = I == 1 ? rows_blocks(O, n, k, ROWS_MIN_TASKS) : 0;
+        // (the same choice as the plain call's launch_bdbs)
         const bool rows_lds = I == 1 && O >= rows_per_task(k) &&
-                              (kb > COOP_CS || rows_tasks(O, n, k, rcb) >= ROWS_MIN_TASKS);
-        if (I == 1 && !rows_lds && !(O < 64 && n > 256) &&
-            narrow_ok(O * n, (int)sizeof(T), 32)) {
-            // rows of the contiguous axis, too few for the LDS-staged tasks
-            // and not a few long ones (those go in chunks, as a strided axis):
-            // one wavefront per task, segmented scans across the lanes
+                              (kb > COOP_CS || n > 256 ||
+                               rows_tasks(O, n, k, rcb) >= ROWS_MIN_TASKS);
+        if (I == 1 && !rows_lds && n <= 256 && narrow_ok(O * n, (int)sizeof(T), 32)) {
+            // short rows of the contiguous axis, too few for the LDS-staged
+            // tasks: one wavefront per task, segmented scans across the lanes
             s.kind = SK_BDBSV;
             s.cb = wave_rows_per_task(O);
             s.ntasks = (O + s.cb - 1) / s.cb * 64;

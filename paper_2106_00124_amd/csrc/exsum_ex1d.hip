@@ -25,7 +25,9 @@ namespace exs {
 
 constexpr int L1_THREADS = 256;
 constexpr int L1_SCAN_THREADS = 1024, L1_SCAN_PER = 8;
-constexpr int L1_MAX_CHUNKS = L1_SCAN_THREADS * L1_SCAN_PER;
+// the chunk-total scan walks tiles of L1_SCAN_THREADS * L1_SCAN_PER totals;
+// at 4096 or more elements per chunk, n < 2^31 stays within this
+constexpr int L1_MAX_CHUNKS = 1 << 19;
 
 // elements per thread: whole k-blocks, at least 16
 static inline int l1_elems(i64 k) { return (int)(k * ((16 + k - 1) / k)); }
@@ -70,36 +72,67 @@ template <typename T, class Op>
 __global__ __launch_bounds__(L1_SCAN_THREADS) void k_l1_scan(const T* __restrict__ Tt,
                                                              T* __restrict__ CP,
                                                              T* __restrict__ CS, int nc) {
-    __shared__ T wt[2][L1_SCAN_THREADS / 64];
+    // tiles of L1_SCAN_THREADS * L1_SCAN_PER chunk totals: forward over the
+    // tiles for the prefixes, backward for the suffixes, each carrying the op
+    // of the tiles already passed
+    constexpr int TILE = L1_SCAN_THREADS * L1_SCAN_PER;
+    constexpr int NW = L1_SCAN_THREADS / 64;
+    __shared__ T wt[NW];
     const T e = Op::template id<T>();
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int b0 = t * L1_SCAN_PER;
-    T v[L1_SCAN_PER];
+    T carry = e;  // op of the chunk totals before the tile
+    for (int base = 0; base < nc; base += TILE) {
+        const int b0 = base + t * L1_SCAN_PER;
+        T v[L1_SCAN_PER];
 #pragma unroll
-    for (int r = 0; r < L1_SCAN_PER; ++r) v[r] = b0 + r < nc ? Tt[b0 + r] : e;
-    T run = e;
+        for (int r = 0; r < L1_SCAN_PER; ++r) v[r] = b0 + r < nc ? Tt[b0 + r] : e;
+        T run = e;
 #pragma unroll
-    for (int r = 0; r < L1_SCAN_PER; ++r) run = Op::apply(run, v[r]);
-    const T ip = wave_prefix<T, Op>(run, lane);
-    const T is = wave_suffix<T, Op>(run, lane);
-    if (lane == 63) wt[0][wv] = ip;
-    if (lane == 0) wt[1][wv] = is;
-    __syncthreads();
-    T lo = e, hi = e;
-    for (int w = 0; w < wv; ++w) lo = Op::apply(lo, wt[0][w]);
-    for (int w = L1_SCAN_THREADS / 64 - 1; w > wv; --w) hi = Op::apply(wt[1][w], hi);
-    const T up = __shfl_up(ip, 1, 64), dn = __shfl_down(is, 1, 64);
-    T before = lane > 0 ? Op::apply(lo, up) : lo;
-    T after = lane < 63 ? Op::apply(dn, hi) : hi;
+        for (int r = 0; r < L1_SCAN_PER; ++r) run = Op::apply(run, v[r]);
+        const T ip = wave_prefix<T, Op>(run, lane);
+        if (lane == 63) wt[wv] = ip;
+        __syncthreads();
+        T lo = e, all = e;
+        for (int w = 0; w < NW; ++w) {
+            if (w < wv) lo = Op::apply(lo, wt[w]);
+            all = Op::apply(all, wt[w]);
+        }
+        const T up = __shfl_up(ip, 1, 64);
+        T before = Op::apply(carry, lane > 0 ? Op::apply(lo, up) : lo);
 #pragma unroll
-    for (int r = 0; r < L1_SCAN_PER; ++r) {
-        if (b0 + r < nc) CP[b0 + r] = before;
-        before = Op::apply(before, v[r]);
+        for (int r = 0; r < L1_SCAN_PER; ++r) {
+            if (b0 + r < nc) CP[b0 + r] = before;
+            before = Op::apply(before, v[r]);
+        }
+        carry = Op::apply(carry, all);
+        __syncthreads();  // wt is rewritten by the next tile
     }
+    carry = e;  // op of the chunk totals after the tile
+    for (int base = (nc - 1) / TILE * TILE; base >= 0; base -= TILE) {
+        const int b0 = base + t * L1_SCAN_PER;
+        T v[L1_SCAN_PER];
 #pragma unroll
-    for (int r = L1_SCAN_PER - 1; r >= 0; --r) {
-        if (b0 + r < nc) CS[b0 + r] = after;
-        after = Op::apply(v[r], after);
+        for (int r = 0; r < L1_SCAN_PER; ++r) v[r] = b0 + r < nc ? Tt[b0 + r] : e;
+        T run = e;
+#pragma unroll
+        for (int r = 0; r < L1_SCAN_PER; ++r) run = Op::apply(run, v[r]);
+        const T is = wave_suffix<T, Op>(run, lane);
+        if (lane == 0) wt[wv] = is;
+        __syncthreads();
+        T hi = e, all = e;
+        for (int w = NW - 1; w >= 0; --w) {
+            if (w > wv) hi = Op::apply(wt[w], hi);
+            all = Op::apply(wt[w], all);
+        }
+        const T dn = __shfl_down(is, 1, 64);
+        T after = Op::apply(lane < 63 ? Op::apply(dn, hi) : hi, carry);
+#pragma unroll
+        for (int r = L1_SCAN_PER - 1; r >= 0; --r) {
+            if (b0 + r < nc) CS[b0 + r] = after;
+            after = Op::apply(v[r], after);
+        }
+        carry = Op::apply(all, carry);
+        __syncthreads();
     }
 }
 

@@ -462,13 +462,14 @@ void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st
     }
     const i64 nb = (n + k - 1) / k;
     const i64 rcb = I == 1 ? rows_blocks(O, n, k, ROWS_MIN_TASKS) : 0;
-    // (boxes over 16: always, the wavefront kernel walks whole rows)
+    // LDS row tiles once there are enough of them to fill the GPU, and
+    // always for boxes over 16 or rows over 256 elements (the wavefront
+    // kernel walks whole rows, block registers grow with the box); short rows
+    // otherwise one wavefront per few rows; a few long rows in chunks (the
+    // generic tasks)
     const bool rows_lds = I == 1 && O >= rows_per_task(k) &&
-                          (kb > COOP_CS || rows_tasks(O, n, k, rcb) >= ROWS_MIN_TASKS);
-    // a few long rows: chunks of the rows in parallel (the generic tasks)
-    // rather than one wavefront walking each row from end to end
-    const bool wave = I == 1 && !rows_lds && !(O < 64 && n > 256) &&
-                      narrow_ok(O * n, (int)sizeof(T), 32);
+                          (kb > COOP_CS || n > 256 || rows_tasks(O, n, k, rcb) >= ROWS_MIN_TASKS);
+    const bool wave = I == 1 && !rows_lds && n <= 256 && narrow_ok(O * n, (int)sizeof(T), 32);
     KTimer timer(I > 1 ? (kb >= 32 ? "k_bdbs_coop" : "k_bdbs")
                        : wave ? "k_bdbs_wave" : "k_bdbs_rows", st);
     if (wave) {

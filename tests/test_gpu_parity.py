@@ -6,6 +6,7 @@ boxes longer than 64 (the two-sweep kernels), ranks 1..8, every dtype x op.
 import numpy as np
 import pytest
 
+from tests import tolerance
 from tests.gpu_util import compare_full, gpu_run, make_input, say, seed_of
 
 pytestmark = pytest.mark.gpu
@@ -224,3 +225,17 @@ def test_weak_max_unsupported():
     for op in ("max", "min"):
         with pytest.raises(ExsError, match="EUNSUPPORTED"):
             P.run(x, (2, 2), op, "weak")
+
+
+@pytest.mark.parametrize("n,k", [(33566777, 7), (73000000, 16)])
+@pytest.mark.parametrize("dtype,op", [("i32", "sum"), ("f32", "max")], ids=lambda v: str(v))
+def test_parity_long1d_many_chunks(orc, n, k, dtype, op):
+    """A 1-D tensor of more chunk totals than one tile of the chunk-total scan
+    (8192): two and three tiles, the carries across them in both directions."""
+    seed = seed_of(n, k, dtype, op, "long1d")
+    say(f"[long1d] n={n} k={k} dtype={dtype} op={op} seed={seed}")
+    a = make_input((n,), dtype, seed=seed, op=op)
+    inc, exc = gpu_run(a, (k,), op, "both")
+    ri, re_ = orc.scale(a, (k,), op, dtype)
+    tolerance.check(inc, ri, dtype, op, what=f"long1d {n} {k} inc")
+    tolerance.check(exc, re_, dtype, op, what=f"long1d {n} {k} exc")
