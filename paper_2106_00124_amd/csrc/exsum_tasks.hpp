@@ -489,28 +489,63 @@ __device__ __forceinline__ void task_bdbs_rows(const T* __restrict__ in, T* __re
     const int wout = (int)(rout < n - col0 ? rout : n - col0);
     constexpr int RPT = rows_per_task_kb(KB);
     const i64 row0 = g * RPT;
-    // stage the tile (identity past the row end and in the unused pitch);
-    // LW <= 127, so two 64-column passes cover a row.  Loads are issued in
-    // batches of RB rows before any of them is written to LDS.
-    constexpr int RB = RPT < 32 ? RPT : 32;
+    // Whole rows (one run of blocks per row): the task's rows are one
+    // contiguous span of the tensor, staged and stored flat (every lane busy
+    // however short the rows); lane f of the span goes to (f / n, f % n),
+    // tracked incrementally.
+    const bool flat = nchunks == 1;
+    const int nn = (int)n;
+    const int vrows = row0 + RPT <= O ? RPT : (int)(O - row0);
+    if (flat) {
+        const T* __restrict__ src = in + row0 * n;
+        const int span = vrows * nn, dr = 64 / nn, dc = 64 % nn;
+        int r = lane / nn, cc = lane % nn;
+        constexpr int U = 8;
+        for (int f0 = 0; f0 < span; f0 += 64 * U) {
+            T v[U];
 #pragma unroll
-    for (int r0 = 0; r0 < RPT; r0 += RB) {
-        T v[RB][2];
+            for (int u = 0; u < U; ++u) {
+                const int f = f0 + 64 * u + lane;
+                v[u] = f < span ? src[f] : e;
+            }
 #pragma unroll
-        for (int rr = 0; rr < RB; ++rr) {
-            const i64 row = row0 + r0 + rr;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int cc = lane + 64 * h;
-                v[rr][h] = (row < O && cc < win) ? in[row * n + col0 + cc] : e;
+            for (int u = 0; u < U; ++u) {
+                if (f0 + 64 * u + lane < span) lds[r * LW + cc] = v[u];
+                r += dr;
+                cc += dc;
+                if (cc >= nn) { cc -= nn; ++r; }
             }
         }
+        // identity in the pitch past the row end and in rows past the tensor
+        for (int rr = 0; rr < RPT; ++rr) {
+            const int c0 = rr < vrows ? nn : 0;
+            for (int c = c0 + lane; c < LW; c += 64) lds[rr * LW + c] = e;
+        }
+    }
+    // otherwise stage the tile (identity past the row end and in the unused
+    // pitch); LW <= 127, so two 64-column passes cover a row.  Loads are
+    // issued in batches of RB rows before any of them is written to LDS.
+    constexpr int RB = RPT < 32 ? RPT : 32;
+    if (!flat) {
 #pragma unroll
-        for (int rr = 0; rr < RB; ++rr) {
+        for (int r0 = 0; r0 < RPT; r0 += RB) {
+            T v[RB][2];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int cc = lane + 64 * h;
-                if (cc < LW) lds[(r0 + rr) * LW + cc] = v[rr][h];
+            for (int rr = 0; rr < RB; ++rr) {
+                const i64 row = row0 + r0 + rr;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int cc = lane + 64 * h;
+                    v[rr][h] = (row < O && cc < win) ? in[row * n + col0 + cc] : e;
+                }
+            }
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int cc = lane + 64 * h;
+                    if (cc < LW) lds[(r0 + rr) * LW + cc] = v[rr][h];
+                }
             }
         }
     }
@@ -599,24 +634,36 @@ __device__ __forceinline__ void task_bdbs_rows(const T* __restrict__ in, T* __re
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int r0 = 0; r0 < RPT; r0 += RB) {
-        T v[RB][2];
-#pragma unroll
-        for (int rr = 0; rr < RB; ++rr) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int cc = lane + 64 * h;
-                v[rr][h] = cc < LW ? lds[(r0 + rr) * LW + cc] : e;
-            }
+    if (flat) {
+        T* __restrict__ dst = out + row0 * n;
+        const int span = vrows * nn, dr = 64 / nn, dc = 64 % nn;
+        int r = lane / nn, cc = lane % nn;
+        for (int f = lane; f < span; f += 64) {
+            dst[f] = lds[r * LW + cc];
+            r += dr;
+            cc += dc;
+            if (cc >= nn) { cc -= nn; ++r; }
         }
+    } else {
 #pragma unroll
-        for (int rr = 0; rr < RB; ++rr) {
-            const i64 row = row0 + r0 + rr;
+        for (int r0 = 0; r0 < RPT; r0 += RB) {
+            T v[RB][2];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int cc = lane + 64 * h;
-                if (row < O && cc < wout) out[row * n + col0 + cc] = v[rr][h];
+            for (int rr = 0; rr < RB; ++rr) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int cc = lane + 64 * h;
+                    v[rr][h] = cc < LW ? lds[(r0 + rr) * LW + cc] : e;
+                }
+            }
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) {
+                const i64 row = row0 + r0 + rr;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int cc = lane + 64 * h;
+                    if (row < O && cc < wout) out[row * n + col0 + cc] = v[rr][h];
+                }
             }
         }
     }
