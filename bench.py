@@ -55,6 +55,12 @@ def parse():
     p.add_argument("--op-costs", type=int, nargs="+", default=[0, 16, 64, 256, 1024, 4096])
     p.add_argument("--op-cost-shape", type=int, nargs="+", default=[128, 128, 128])
     p.add_argument("--op-cost-box", type=int, nargs="+", default=[4, 4, 4])
+    p.add_argument("--case", type=str, default=None,
+                   help="time one plain call instead of the default step: comma-separated "
+                        "fp32 shape (device counter fill), with --box, --op and --mode")
+    p.add_argument("--box", type=str, default=None, help="comma-separated box for --case")
+    p.add_argument("--op", type=str, default="sum", help="operator for --case")
+    p.add_argument("--mode", type=str, default="both", help="mode for --case (inc, exc, both)")
     p.add_argument("--no-corners", action="store_true",
                    help="skip the corners-algorithm comparison (2-D)")
     p.add_argument("--sweep-corners", action="store_true",
@@ -194,6 +200,9 @@ def main():
         return
     if args.sweep_op_cost:
         sweep_op_cost(args, P, torch, np)
+        return
+    if args.case:
+        bench_case(args, P, torch, np)
         return
     if args.sweep_corners:
         for n in (1024, 4096, 8192, 16384):
@@ -637,6 +646,68 @@ def sweep_n(args, P, torch, np):
     print(json.dumps({"metric": "excluded-sum Gelem/s vs N (fp32 cubes, box 16^3, +)",
                       "unit": "Gelem/s", "n_gpus": 1, "data": "synthetic", "sweep": rows}),
           flush=True)
+
+
+def bench_case(args, P, torch, np):
+    """One plain call on an fp32 tensor of the given shape (device counter
+    fill, unit variance), timed over --steps calls after --warmup, with the
+    per-kernel breakdown from the library's event timing and a check of
+    sampled cells against the oracle."""
+    import oracle
+    from tests import tolerance
+    from paper_2106_00124_amd import _lib, workloads as W
+    shape = tuple(int(v) for v in args.case.split(","))
+    box = tuple(int(v) for v in args.box.split(",")) if args.box else (8,) * len(shape)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    x = torch.empty(shape, dtype=torch.float32, device=dev)
+    seed = 300 + len(shape)
+    P.fill(x, W.FILL_NORMALISH, seed)
+    ws = torch.empty(max(P.workspace_size(shape, box, torch.float32, args.op, args.mode), 1),
+                     dtype=torch.uint8, device=dev)
+    inc, exc = torch.empty_like(x), torch.empty_like(x)
+
+    def call():
+        P.run(x, box, args.op, args.mode, inc_out=inc, exc_out=exc, workspace=ws, stream=stream)
+
+    for _ in range(max(1, args.warmup)):
+        call()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        call()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    L = _lib.lib()
+    L.exs_timing_enable(1)
+    read_timings(L)
+    for _ in range(args.steps):
+        call()
+    torch.cuda.synchronize()
+    L.exs_timing_enable(0)
+    kt = read_timings(L)
+    N = x.numel()
+    res = {"shape": list(shape), "box": list(box), "op": args.op, "mode": args.mode,
+           "dtype": "f32", "ms": round(ms, 4), "gelem_per_s": round(N / (ms * 1e-3) / 1e9, 2),
+           "kernels_us": {k: round(t / n * 1e3, 1) for k, (n, t) in kt.items()},
+           "launches_per_call": {k: n // args.steps for k, (n, t) in kt.items()}}
+    if not args.no_check and args.mode in ("exc", "both"):
+        o = oracle.default()
+        host = W.counter_fill(W.FILL_NORMALISH, "f32", N, seed).reshape(shape)
+        pts = np.random.default_rng(seed).integers(0, N, 64)
+        got = exc.reshape(-1)[torch.from_numpy(pts).to(dev)].cpu().numpy()
+        ref = o.point_exc(host, box, args.op, "f32", pts)
+        sig = tolerance.sigma_points(o, host, box, "exc", pts) if args.op == "sum" else None
+        try:
+            tolerance.check(got, ref, "f32", args.op, sig)
+            res["check"] = "ok (64 sampled excluded cells)"
+        except AssertionError as err:
+            res["check"] = str(err)[:160]
+    log(f"case {shape} {box} {args.op} {args.mode}: {ms:.4f} ms")
+    print(json.dumps(res), flush=True)
 
 
 def bench_configs(args, P, torch, np):
