@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_bdbs_coop(const T* __restrict__ in, T* 
     if (task < ntasks) task_bdbs_coop<T, Op, KB>(in, out, O, n, I, k, cb, task);
 }
 
-template <typename T, class Op, int KB>
+template <typename T, class Op, int KB, int OUT>
 __global__ __launch_bounds__(256) void k_axis0_coop(const T* __restrict__ W,
                                                     const T* __restrict__ PX,
                                                     const T* __restrict__ SX,
@@ -64,7 +64,8 @@ __global__ __launch_bounds__(256) void k_axis0_coop(const T* __restrict__ W,
                                                     i64 ntasks) {
     const i64 task = ((i64)blockIdx.x * 256 + threadIdx.x) >> 6;
     if (task < ntasks)
-        task_axis0_coop<T, Op, KB>(W, PX, SX, Trest, exc, inc, n0, M, k0, Q, segblocks, task);
+        task_axis0_coop<T, Op, KB, OUT>(W, PX, SX, Trest, exc, inc, n0, M, k0, Q, segblocks,
+                                        task);
 }
 
 // Wavefront tasks of the split-block kernels: enough runs along the axis that
@@ -761,19 +762,27 @@ void launch_axis0(const T* W, const T* PX, const T* SX, const T* Trest, T* exc, 
         return;
     }
     if (kb >= 32 && n0 * M * (i64)sizeof(T) < ((i64)1 << 31)) {
-        // boxes of 17 to 64 along axis 0: lanes share a point
+        // boxes of 17 to 64 along axis 0: lanes share a point; one output
+        // or both (OUT: 1 excluded, 2 included, 3 both)
+        const int out = (exc ? 1 : 0) | (inc ? 2 : 0);
         i64 tasks = 0;
-        const i64 C = 64 / coop_g(kb, (int)sizeof(T), true);
+        const i64 C = 64 / coop_g_ax0(kb, (int)sizeof(T), out);
         const i64 segblocks = coop_runs((M + C - 1) / C, Q, &tasks);
         KTimer timer("k_axis0_coop", st);
-        if (kb == 32)
-            hipLaunchKernelGGL((k_axis0_coop<T, Op, 32>), dim3(grid_for(tasks * 64)), dim3(256), 0,
-                               st, W, PX, SX, Trest, exc, inc, n0, M, (int)k0, Q, segblocks,
-                               tasks);
-        else
-            hipLaunchKernelGGL((k_axis0_coop<T, Op, 64>), dim3(grid_for(tasks * 64)), dim3(256), 0,
-                               st, W, PX, SX, Trest, exc, inc, n0, M, (int)k0, Q, segblocks,
-                               tasks);
+        const dim3 grid(grid_for(tasks * 64));
+#define EXS_AX0C(KB, OUT)                                                                     \
+    hipLaunchKernelGGL((k_axis0_coop<T, Op, KB, OUT>), grid, dim3(256), 0, st, W, PX, SX,      \
+                       Trest, exc, inc, n0, M, (int)k0, Q, segblocks, tasks)
+        if (kb == 32) {
+            if (out == 1) EXS_AX0C(32, 1);
+            else if (out == 2) EXS_AX0C(32, 2);
+            else EXS_AX0C(32, 3);
+        } else {
+            if (out == 1) EXS_AX0C(64, 1);
+            else if (out == 2) EXS_AX0C(64, 2);
+            else EXS_AX0C(64, 3);
+        }
+#undef EXS_AX0C
         return;
     }
     i64 nseg = (65536 + M - 1) / M;

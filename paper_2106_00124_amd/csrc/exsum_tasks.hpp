@@ -394,6 +394,11 @@ constexpr int COOP_CS = 16;  // slots per lane of the LDS-staged row tasks
 __host__ __device__ constexpr int coop_g(int kb, int es, bool axis0) {
     return (kb == 64 && (axis0 || es == 8)) ? 4 : 2;
 }
+// ... for the axis-0 stream with one output (OUT 1: excluded sums, 2:
+// included sums), which carries one block array less than with both (OUT 3)
+__host__ __device__ constexpr int coop_g_ax0(int kb, int es, int out) {
+    return out == 3 ? coop_g(kb, es, true) : coop_g(kb, es, false);
+}
 
 // ADJ: the G lanes of a column are adjacent (lane = c * G + g) -- for
 // operands staged in LDS, where no load coalescing is at stake.
@@ -845,14 +850,14 @@ __device__ __forceinline__ void task_bdbs_coop(const T* __restrict__ in, T* __re
 // row of the next block on, and SX beyond that; Trest folded into the
 // running prefix) and included sums (BDBS along axis 0).  Task = (run of
 // `segblocks` blocks, group of C points), the group fastest.
-template <typename T, class Op, int KB>
+template <typename T, class Op, int KB, int OUT>
 __device__ __forceinline__ void task_axis0_coop(const T* __restrict__ W, const T* __restrict__ PX,
                                                 const T* __restrict__ SX,
                                                 const T* __restrict__ Trest,
                                                 T* __restrict__ exc, T* __restrict__ inc,
                                                 i64 n0_, i64 M_, int k0, i64 Q_, i64 segblocks,
                                                 i64 task) {
-    constexpr int G = coop_g(KB, sizeof(T), true), CS = KB / G;
+    constexpr int G = coop_g_ax0(KB, sizeof(T), OUT), CS = KB / G;
     using L = CoopLanes<T, Op, G>;
     constexpr int C = L::C;
     const L ln(threadIdx.x & 63);
@@ -878,8 +883,90 @@ __device__ __forceinline__ void task_axis0_coop(const T* __restrict__ W, const T
     const unsigned base = mo + (unsigned)(ln.g * CS) * rowb;
     auto lim_of = [&](int q) { return live ? min(k0, n0 - q * k0) - ln.g * CS : 0; };
 
-    // w: raw values of the held block q; wb, wa: op of its other segments
-    // before / after this lane's; wt: op of the whole block
+    if constexpr (OUT == 1 || OUT == 2) {
+        // one output: the held block q is kept as the one scan that output
+        // needs of it -- its exclusive prefixes from the block start
+        // (excluded sums) or its range suffixes (included sums)
+        T h[CS], v[CS];
+        T hb, ha, ht;  // op of the held block's segments before / after this lane's, of all
+        coop_load<T, Op, CS>(rw, base + (unsigned)(qa * k0) * rowb, rowb, lim_of(qa), v);
+        {
+            T tot = e;
+#pragma unroll
+            for (int s = 0; s < CS; ++s) tot = Op::apply(tot, v[s]);
+            ln.scan(tot, hb, ha);
+            ht = Op::apply(Op::apply(hb, tot), ha);
+        }
+        T Pb = e;
+        if constexpr (OUT == 1) {
+            T p = hb;
+#pragma unroll
+            for (int s = 0; s < CS; ++s) {
+                h[s] = p;
+                p = Op::apply(p, v[s]);
+            }
+            Pb = bload<T>(buf(PX, qbytes), mo + (unsigned)qa * rowb);
+            if (Trest) Pb = Op::apply(Pb, bload<T>(buf(Trest, rowb), mo));
+            if (!live) Pb = e;
+        } else {
+            T sf = ha;
+#pragma unroll
+            for (int s = CS - 1; s >= 0; --s) {
+                sf = Op::apply(v[s], sf);
+                h[s] = sf;
+            }
+        }
+        for (int q = qa; q < qb; ++q) {
+            const int limn = q + 1 < Q ? lim_of(q + 1) : 0;
+            coop_load<T, Op, CS>(rw, base + (unsigned)((q + 1) * k0) * rowb, rowb, limn, v);
+            T vt = e;
+#pragma unroll
+            for (int s = 0; s < CS; ++s) vt = Op::apply(vt, v[s]);
+            T vb, va;
+            ln.scan(vt, vb, va);
+            const int limc = lim_of(q);
+            const unsigned oc = base + (unsigned)(q * k0) * rowb;
+            if constexpr (OUT == 1) {
+                // everything before the row (Pb, then the held block's prefix),
+                // then block q + 1 from the same slot on and the blocks after it
+                const T sxv = bload<T>(rsx, mo + (unsigned)(q + 1) * rowb);
+                T sf = Op::apply(va, (q + 1 < Q && live) ? sxv : e);
+#pragma unroll
+                for (int s = CS - 1; s >= 0; --s) {
+                    sf = Op::apply(v[s], sf);
+                    bstore<T>(rex, s < limc ? oc + (unsigned)s * rowb : NOWHERE,
+                              Op::apply(Op::apply(Pb, h[s]), sf));
+                }
+                Pb = Op::apply(Pb, ht);
+                T p = vb;
+#pragma unroll
+                for (int s = 0; s < CS; ++s) {
+                    h[s] = p;
+                    p = Op::apply(p, v[s]);
+                }
+            } else {
+                // range suffix of block q op range prefix of block q + 1
+                T p = vb;
+#pragma unroll
+                for (int s = 0; s < CS; ++s) {
+                    bstore<T>(rin, s < limc ? oc + (unsigned)s * rowb : NOWHERE,
+                              Op::apply(h[s], p));
+                    p = Op::apply(p, v[s]);
+                }
+                T sf = va;
+#pragma unroll
+                for (int s = CS - 1; s >= 0; --s) {
+                    sf = Op::apply(v[s], sf);
+                    h[s] = sf;
+                }
+            }
+            ht = Op::apply(Op::apply(vb, vt), va);
+        }
+        return;
+    }
+    // both outputs (or either, decided at run time): w holds the raw values
+    // of the held block q; wb, wa: op of its other segments before / after
+    // this lane's; wt: op of the whole block
     T w[CS], v[CS], t[CS];
     T wb, wa, wt;
     coop_load<T, Op, CS>(rw, base + (unsigned)(qa * k0) * rowb, rowb, lim_of(qa), w);
@@ -975,7 +1062,7 @@ __device__ __forceinline__ void run_task(const Step& s, i64 i) {
         task_bdbs_coop<T, Op, KB>((const T*)s.in0, (T*)s.out0, s.O, s.n, s.I, s.k, s.cb,
                                   i >> 6);
     else if constexpr (KIND == SK_AX0C)
-        task_axis0_coop<T, Op, KB>(
+        task_axis0_coop<T, Op, KB, 3>(
             (const T*)s.in0, (const T*)s.in1, (const T*)s.in2, (const T*)s.in3, (T*)s.out0,
             (T*)s.out1, s.n, s.I, s.k, s.Q, s.cb, i >> 6);
     else if constexpr (KIND == SK_AX0 || KIND == SK_AX0W)

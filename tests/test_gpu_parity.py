@@ -239,3 +239,25 @@ def test_parity_long1d_many_chunks(orc, n, k, dtype, op):
     ri, re_ = orc.scale(a, (k,), op, dtype)
     tolerance.check(inc, ri, dtype, op, what=f"long1d {n} {k} inc")
     tolerance.check(exc, re_, dtype, op, what=f"long1d {n} {k} exc")
+
+
+# one output at a time through the axis-0 stream for boxes of 17 to 64 along
+# axis 0 (the single-output forms keep one block array, not two)
+AX0_ONE_OUTPUT = [
+    ((200, 33, 40), (40, 3, 5)),
+    ((130, 70), (64, 2)),
+    ((3000, 5), (33, 2)),
+    ((90, 16, 16), (17, 1, 1)),
+]
+
+
+@pytest.mark.parametrize("mode", ["inc", "exc"])
+@pytest.mark.parametrize("shape,box", AX0_ONE_OUTPUT, ids=lambda v: "x".join(map(str, v)))
+@pytest.mark.parametrize("dtype,op", [("f32", "sum"), ("i32", "max"), ("f64", "min")],
+                         ids=lambda v: str(v))
+def test_parity_axis0_one_output(orc, mode, shape, box, dtype, op):
+    seed = seed_of(shape, box, dtype, op, mode, "ax0one")
+    say(f"[ax0-one] shape={shape} box={box} dtype={dtype} op={op} mode={mode} seed={seed}")
+    a = make_input(shape, dtype, seed=seed, op=op)
+    inc, exc = gpu_run(a, box, op, mode)
+    compare_full(orc, a, box, op, dtype, inc, exc, what=f"{shape} {box} {dtype} {op} {mode}")
