@@ -170,6 +170,11 @@ struct EagerSink {
     void blockagg(const T* X, T* Ga, i64 n0, i64 M, i64 k0, i64 Q) {
         launch_blockagg<T, Op>(X, Ga, n0, M, k0, Q, st);
     }
+    bool aggmid_ok() const { return true; }
+    void aggmid(const T* A, T* X, T* Ga, T* G1, i64 n0, i64 P, i64 nf, i64 S, i64 k0, i64 kf,
+                i64 Q) {
+        launch_aggmid<T, Op>(A, X, Ga, G1, n0, P, nf, S, k0, kf, Q, st);
+    }
     bool small1d_ok(i64 n) const { return ex1d_small_ok(n); }
     i64 tail_box_max() const { return tail_box_max_elems((int)sizeof(T)); }
     void bdbs_tail(const T* in, T* out, i64 O, int m, const i64* n, const i64* k) {

@@ -61,6 +61,9 @@ struct ListSink {
     void row_axis0(const T*, const T*, const T*, const T*, T*, T*, i64, i64, i64, i64, i64) {}
     // the single-workgroup kernel for a short last level has no work-list form
     bool small1d_ok(i64) const { return false; }
+    // the fused levels are off here, and with them the fused aggregate pass
+    bool aggmid_ok() const { return false; }
+    void aggmid(const T*, T*, T*, T*, i64, i64, i64, i64, i64, i64, i64) {}
     // the staged multi-axis BDBS has no work-list form
     i64 tail_box_max() const { return 0; }
     void bdbs_tail(const T*, T*, i64, int, const i64*, const i64*) {}

@@ -91,6 +91,11 @@ template <typename T, class Op>
 void launch_ex1d_small(const T* R, T* exc, i64 n, i64 k, hipStream_t st);
 template <typename T, class Op>
 void launch_blockagg(const T* X, T* Ga, i64 n0, i64 M, i64 k0, i64 Q, hipStream_t st);
+// block aggregates along axis 0 fused with BDBS along the middle axis f of an
+// (n0, P, nf, S) tensor (kf from 2 to 16): X = BDBS_f(A), Ga, G1 = BDBS_f(Ga)
+template <typename T, class Op>
+void launch_aggmid(const T* A, T* X, T* Ga, T* G1, i64 n0, i64 P, i64 nf, i64 S, i64 k0, i64 kf,
+                   i64 Q, hipStream_t st);
 template <typename T, class Op>
 void launch_blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M,
                       hipStream_t st);

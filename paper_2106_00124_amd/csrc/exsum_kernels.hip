@@ -81,6 +81,143 @@ static inline i64 coop_runs(i64 groups, i64 nb, i64* ntasks) {
     return per;
 }
 
+// Block aggregates along axis 0 fused with BDBS along one middle axis f, for
+// the fused levels of rank >= 4 (P1 needs Ga and BDBS_f(Ga), P2 needs
+// BDBS_f of the tensor itself; box sums along different axes commute, so
+// BDBS_f(Ga) is the block aggregate of BDBS_f(A)).  The tensor is viewed as
+// (n0, P, nf, S); one thread per (block q of axis 0, p, run of CB blocks of
+// axis f, s), s fastest: it walks the k0 rows of block q, box-sums each
+// along f (writing X) and keeps the op over the rows of every slot of the
+// run and of its lookahead block in registers, which it stores as Ga and
+// box-sums into G1.  One read of the tensor instead of two, and no pass over
+// Ga.
+template <int KB>
+struct AggMid {
+    static constexpr int CB = KB >= 16 ? 1 : KB >= 8 ? 2 : 4;  // blocks of f per run
+};
+
+template <typename T, class Op, int KB>
+__device__ __forceinline__ void am_suffix(T (&v)[KB], int k) {
+    T s = Op::template id<T>();
+#pragma unroll
+    for (int r = KB - 1; r >= 0; --r)
+        if (r < k) {
+            s = Op::apply(v[r], s);
+            v[r] = s;
+        }
+}
+
+template <typename T, class Op, int KB>
+__global__ __launch_bounds__(256) void k_aggmid(const T* __restrict__ A, T* __restrict__ X,
+                                               T* __restrict__ Ga, T* __restrict__ G1, i64 n0,
+                                               i64 P, i64 nf, i64 S, int k0, int kf, i64 Q,
+                                               i64 nruns) {
+    constexpr int CB = AggMid<KB>::CB;
+    constexpr unsigned es = sizeof(T);
+    const i64 idx = gtid();
+    const i64 s = idx % S;
+    i64 rest = idx / S;
+    const i64 c = rest % nruns;
+    rest /= nruns;
+    const i64 p = rest % P;
+    const i64 q = rest / P;
+    if (q >= Q) return;
+    const T e = Op::template id<T>();
+    const int nbf = (int)((nf + kf - 1) / kf);
+    const int b0 = (int)c * CB;
+    const int nb = nbf - b0 < CB ? nbf - b0 : CB;  // blocks of this run, >= 1
+    // 32-bit byte offsets (tensors below 2^31 bytes): a slot's row along f is
+    // a uniform scalar offset, the lane's column and block base a vector one
+    const unsigned nbytes = (unsigned)(n0 * P * nf * S * (i64)es);
+    const unsigned gbytes = (unsigned)(Q * P * nf * S * (i64)es);
+    const __amdgpu_buffer_rsrc_t ra = buf(A, nbytes), rx = buf(X, nbytes);
+    const __amdgpu_buffer_rsrc_t rg = buf(Ga, gbytes), rg1 = buf(G1, gbytes);
+    const unsigned sb = (unsigned)(S * (i64)es);  // bytes between slots along f
+    const unsigned rowb = (unsigned)(nf * S * (i64)es);
+    const int lim_last = (int)(nf - (i64)(nbf - 1) * kf);  // slots of the last block
+    auto lim = [&](int b) { return b < nbf - 1 ? kf : (b == nbf - 1 ? lim_last : 0); };
+    T acc[CB + 1][KB];
+#pragma unroll
+    for (int i = 0; i <= CB; ++i)
+#pragma unroll
+        for (int j = 0; j < KB; ++j) acc[i][j] = e;
+    const i64 t0 = q * k0;
+    const int rows = (int)(n0 - t0 < k0 ? n0 - t0 : k0);
+    const unsigned col = (unsigned)(s * (i64)es);
+    for (int r = 0; r < rows; ++r) {
+        const unsigned base = (unsigned)(((t0 + r) * P + p) * (i64)rowb) + col;
+        T cur[KB], nxt[KB];
+        {
+            const int l = lim(b0);
+            const unsigned ob = base + (unsigned)(b0 * kf) * sb;
+#pragma unroll
+            for (int j = 0; j < KB; ++j) {
+                const T v = bload_s<T>(ra, ob, (unsigned)j * sb);
+                cur[j] = j < l ? v : e;
+                acc[0][j] = Op::apply(acc[0][j], cur[j]);
+            }
+        }
+        am_suffix<T, Op, KB>(cur, kf);
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
+            if (i < nb) {
+                const int b = b0 + i;
+                const int ln = lim(b + 1), lc = lim(b);
+                const unsigned on = base + (unsigned)((b + 1) * kf) * sb;
+                const unsigned oc = base + (unsigned)(b * kf) * sb;
+#pragma unroll
+                for (int j = 0; j < KB; ++j) {
+                    const T v = bload_s<T>(ra, on, (unsigned)j * sb);
+                    nxt[j] = j < ln ? v : e;
+                    acc[i + 1][j] = Op::apply(acc[i + 1][j], nxt[j]);
+                }
+                // range suffix of block b op range prefix of block b + 1
+                T pp = e;
+#pragma unroll
+                for (int j = 0; j < KB; ++j) {
+                    T v = cur[j];
+                    if (j > 0) {
+                        pp = Op::apply(pp, nxt[j - 1]);
+                        v = Op::apply(v, pp);
+                    }
+                    bstore<T>(rx, j < lc ? oc + (unsigned)j * sb : NOWHERE, v);
+                }
+#pragma unroll
+                for (int j = 0; j < KB; ++j) cur[j] = nxt[j];
+                am_suffix<T, Op, KB>(cur, kf);
+            }
+        }
+    }
+    // the run's block aggregates, and their box sums along f
+    const unsigned gbase = (unsigned)((q * P + p) * (i64)rowb) + col;
+    T cur[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) cur[j] = acc[0][j];
+    am_suffix<T, Op, KB>(cur, kf);
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+        if (i < nb) {
+            const int b = b0 + i, lc = lim(b);
+            const unsigned oc = gbase + (unsigned)(b * kf) * sb;
+            T pp = e;
+#pragma unroll
+            for (int j = 0; j < KB; ++j) {
+                const unsigned o = j < lc ? oc + (unsigned)j * sb : NOWHERE;
+                bstore<T>(rg, o, acc[i][j]);
+                T v = cur[j];
+                if (j > 0) {
+                    pp = Op::apply(pp, acc[i + 1][j - 1]);
+                    v = Op::apply(v, pp);
+                }
+                bstore<T>(rg1, o, v);
+            }
+#pragma unroll
+            for (int j = 0; j < KB; ++j) cur[j] = acc[i + 1][j];
+            am_suffix<T, Op, KB>(cur, kf);
+        }
+    }
+}
+
 template <typename T, class Op, int KB>
 __global__ __launch_bounds__(64) void k_bdbs_rows(const T* __restrict__ in, T* __restrict__ out,
                                                   i64 O, i64 n, int k, i64 cb, i64 nchunks) {
@@ -727,6 +864,25 @@ void launch_blockagg(const T* X, T* Ga, i64 n0, i64 M, i64 k0, i64 Q, hipStream_
 }
 
 template <typename T, class Op>
+void launch_aggmid(const T* A, T* X, T* Ga, T* G1, i64 n0, i64 P, i64 nf, i64 S, i64 k0, i64 kf,
+                   i64 Q, hipStream_t st) {
+    KTimer timer("k_aggmid", st);
+    const int kb = bucket_for(kf);
+    const i64 nbf = (nf + kf - 1) / kf;
+#define EXS_AGGMID(KB)                                                                          \
+    case KB: {                                                                                  \
+        const i64 nruns = (nbf + AggMid<KB>::CB - 1) / AggMid<KB>::CB;                          \
+        hipLaunchKernelGGL((k_aggmid<T, Op, KB>), dim3(grid_for(Q * P * nruns * S)), dim3(256), \
+                           0, st, A, X, Ga, G1, n0, P, nf, S, (int)k0, (int)kf, Q, nruns);      \
+        break;                                                                                  \
+    }
+    switch (kb) {
+        EXS_AGGMID(2) EXS_AGGMID(4) EXS_AGGMID(8) EXS_AGGMID(16)
+    }
+#undef EXS_AGGMID
+}
+
+template <typename T, class Op>
 void launch_blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M,
                       hipStream_t st) {
     KTimer timer("k_blockscan", st);
@@ -826,6 +982,8 @@ void launch_fill(void* out, i64 count, int dtype, int kind, uint64_t seed, i64 l
                                        hipStream_t);                                           \
     template void launch_bdbs<T, OP>(const T*, T*, i64, i64, i64, i64, hipStream_t);           \
     template void launch_blockagg<T, OP>(const T*, T*, i64, i64, i64, i64, hipStream_t);       \
+    template void launch_aggmid<T, OP>(const T*, T*, T*, T*, i64, i64, i64, i64, i64, i64, i64,  \
+                                       hipStream_t);                                           \
     template void launch_blockscan<T, OP>(const T*, const T*, T*, T*, T*, i64, i64,            \
                                           hipStream_t);                                        \
     template void launch_axis0<T, OP>(const T*, const T*, const T*, const T*, T*, T*, i64, i64, \

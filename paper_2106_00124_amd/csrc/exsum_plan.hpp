@@ -266,6 +266,29 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
         d >= 3 && plane2_eligible(n[d - 2], n[d - 1], k[d - 2], k[d - 1], (int)sizeof(T));
     bool scan[EXS_MAX_RANK] = {};
     for (int j = 0; j < d; ++j) scan[j] = fz[j] && Q[j] <= 64 && p2ok;
+    // a fused level of rank >= 4 takes its block aggregates in the same pass
+    // as its box sums along the innermost middle axis f with k > 1 (k <= 16):
+    // that pass writes the box-summed tensor for P2 (xa), Ga, and Ga box-summed
+    // along f (g1a); the other middle axes stay separate passes
+    int amf[EXS_MAX_RANK] = {};  // f relative to the level, 0: not taken
+    T* xa[EXS_MAX_RANK] = {};
+    T* g1a = nullptr;
+    for (int j = 0; j < d; ++j) {
+        const int dj = d - j;
+        // (4-byte fused levels below 2^31 bytes: 32-bit offsets)
+        if (!(fz[j] && p2ok && dj >= 4 && sink.aggmid_ok() &&
+              prod(n, j, d) * (i64)sizeof(T) < ((i64)1 << 31)))
+            continue;
+        for (int a = dj - 3; a >= 1; --a)
+            if (k[j + a] > 1) {
+                if (k[j + a] <= 16) amf[j] = a;
+                break;
+            }
+        if (amf[j]) {
+            xa[j] = ar.take<T>(prod(n, j, d));
+            if (!g1a) g1a = ar.take<T>(maxQM);
+        }
+    }
     // the rank-3 level d - 3, when it takes that pass, also reduces R_{d-2}
     // over the blocks of level d - 2 (its tiles hold whole blocks); when that
     // table is small one workgroup finishes the last two levels from it
@@ -280,17 +303,29 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
         const T* src = j == 0 ? A : R[j];
         if (j == d - 1 && (last_small || last_long)) break;
         sink.level(j);
-        if (!dry) sink.blockagg(src, Ga, n[j], M[j], k[j], Q[j]);
+        const int f = amf[j];
+        if (!dry) {
+            if (f)
+                sink.aggmid(src, xa[j], Ga, g1a, n[j], prod(n, j + 1, j + f), n[j + f],
+                            prod(n, j + f + 1, d), k[j], k[j + f], Q[j]);
+            else
+                sink.blockagg(src, Ga, n[j], M[j], k[j], Q[j]);
+        }
         i64 gn[EXS_MAX_RANK], gk[EXS_MAX_RANK];
         gn[0] = Q[j];
         gk[0] = 1;
         for (int a = 1; a < dj; ++a) { gn[a] = n[j + a]; gk[a] = k[j + a]; }
         const T* Gw;
         const i64 mid = prod(n, j + 1, d - 2);
+        // Ga box-summed over the middle axes
+        auto mid_sums = [&]() {
+            return f ? filter_axes<T>(g1a, gn, gk, dj, 1, f - 1, gb0, gb1, dry, sink)
+                     : filter_axes<T>(Ga, gn, gk, dj, 1, dj - 3, gb0, gb1, dry, sink);
+        };
         if (scan[j]) {
             // middle axes by the generic passes; the two trailing axes and the
             // block scans in one pass (the box-summed planes are not stored)
-            const T* G1 = filter_axes<T>(Ga, gn, gk, dj, 1, dj - 3, gb0, gb1, dry, sink);
+            const T* G1 = mid_sums();
             const bool last3 = tail && j == d - 3;
             // the streaming kernel reads the block prefix only where its runs start
             if (!dry)
@@ -312,7 +347,7 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
         if (fz[j] && p2ok) {
             // middle axes by the generic passes, the two trailing axes in one
             // LDS-tiled pass
-            const T* G1 = filter_axes<T>(Ga, gn, gk, dj, 1, dj - 3, gb0, gb1, dry, sink);
+            const T* G1 = mid_sums();
             T* G2 = G1 == gb0 ? gb1 : gb0;
             if (!dry)
                 sink.plane_bdbs(G1, G2, Q[j] * mid, n[d - 2], n[d - 1], k[d - 2], k[d - 1]);
@@ -341,7 +376,10 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
             continue;
         }
         if (fz[j]) {
-            const T* X0 = filter_axes<T>(src, n + j, k + j, dj, 1, dj - 3, wb0, wb1, dry, sink);
+            const T* X0 = amf[j] ? filter_axes<T>(xa[j], n + j, k + j, dj, 1, amf[j] - 1, wb0,
+                                                  wb1, dry, sink)
+                                 : filter_axes<T>(src, n + j, k + j, dj, 1, dj - 3, wb0, wb1,
+                                                  dry, sink);
             if (!dry)
                 sink.plane_axis0(X0, PX[j], SX[j], Trest, out, j == 0 ? inc : nullptr, n[j],
                                  prod(n, j + 1, d - 2), n[d - 2], n[d - 1], k[j], k[d - 2],

@@ -138,6 +138,16 @@ PLANE_CASES = [
     ((4, 160, 2048), (2, 16, 16)),
     # 64 tiles: four runs of eight blocks along axis 0
     ((64, 256, 256), (2, 16, 16)),
+    # rank >= 4: the block aggregates taken with the box sums along the
+    # innermost middle axis with k > 1 (runs of 1, 2 or 4 of its blocks, a
+    # ragged last block, a middle axis with k = 1 skipped, the other middle
+    # axes as separate passes, a partial last block of axis 0, k0 = 1)
+    ((20, 37, 40, 30), (3, 5, 6, 7)),
+    ((19, 9, 70, 40, 30), (4, 3, 16, 5, 6)),
+    ((18, 41, 1, 50, 40), (5, 9, 1, 4, 4)),
+    ((17, 6, 7, 5, 30, 40), (2, 2, 3, 1, 3, 4)),
+    ((33, 12, 25, 36), (1, 11, 2, 3)),
+    ((10, 50, 35, 33), (8, 2, 4, 5)),
 ]
 
 
