@@ -174,6 +174,17 @@ __device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, unsigned vof
     static_assert(sizeof(T) == 4, "4-byte elements");
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, 0, 2);
 }
+// Output stores of the streaming kernels, with the hint or without.  The
+// hint pays where every output row is a whole number of 64-byte chunks.
+// Rows of other lengths leave chunks at tile edges that two workgroups fill
+// in parts; stored without the hint, the parts meet in L2 and reach memory
+// as one write instead of two partial ones.
+template <typename T, bool NT>
+__device__ __forceinline__ void bstore_h(__amdgpu_buffer_rsrc_t r, unsigned voff, T v) {
+    if constexpr (NT) bstore_nt<T>(r, voff, v);
+    else bstore<T>(r, voff, v);
+}
+inline bool store_hint_ok(long long row_bytes) { return row_bytes % 64 == 0; }
 // A byte offset no descriptor of a tensor below 2^31 bytes covers: a store
 // there is dropped.
 constexpr unsigned NOWHERE = 0x80000000u;

@@ -43,6 +43,7 @@ struct PlaneArgs {
     void* wexc;         // weak excluded sums: (n0, M) total minus included, or null
     i64 n0, MID, NY, NX, M, Q;
     int k0, ky, kx;
+    int nt;             // output stores carry the non-temporal hint
     i64 tilesY, tilesX, segblocks, nseg;
 };
 
@@ -243,7 +244,8 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
     // Emit block (q-1) from w and the ring holding block q, then keep block q.
     // Ring slots past k0, and past the end of the tensor, hold the identity;
     // rows of block q-1 past the tensor end fall outside the store range.
-    auto block_step = [&](int q) __attribute__((always_inline)) {
+    auto block_step_h = [&](int q, auto ntc) __attribute__((always_inline)) {
+        constexpr bool NTS = decltype(ntc)::value;
         __syncthreads();
         T v[K0B];
 #pragma unroll
@@ -263,7 +265,7 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
 #pragma unroll
                 for (int r = K0B - 1; r >= 0; --r) {
                     S = Op::apply(v[r], S);
-                    bstore_nt<T>(ob, mb + (unsigned)r * plane_bytes, Op::apply(tmp[r], S));
+                    bstore_h<T, NTS>(ob, mb + (unsigned)r * plane_bytes, Op::apply(tmp[r], S));
                 }
             }
             if (do_inc || WEAK) {
@@ -281,9 +283,9 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
                 for (int r = 0; r < K0B; ++r) {
                     T val = tmp[r];
                     if (r > 0) { p = Op::apply(p, v[r - 1]); val = Op::apply(val, p); }
-                    if (do_inc) bstore_nt<T>(ob, mb + (unsigned)r * plane_bytes, val);
+                    if (do_inc) bstore_h<T, NTS>(ob, mb + (unsigned)r * plane_bytes, val);
                     if constexpr (WEAK)
-                        bstore_nt<T>(ow, mb + (unsigned)r * plane_bytes, Op::inverse(wtot, val));
+                        bstore_h<T, NTS>(ow, mb + (unsigned)r * plane_bytes, Op::inverse(wtot, val));
                 }
             }
         }
@@ -291,6 +293,10 @@ __global__ void __launch_bounds__(1024) k_plane_axis0(PlaneArgs a) {
 #pragma unroll
             for (int r = 0; r < K0B; ++r) w[r] = v[r];
         }
+    };
+    auto block_step = [&](int q) __attribute__((always_inline)) {
+        if (a.nt) block_step_h(q, std::true_type{});
+        else block_step_h(q, std::false_type{});
     };
     auto ring_fill_identity = [&](int from) {
         for (int r = from; r < K0B; ++r) ring[r * NT + tid] = e;
@@ -851,6 +857,7 @@ void launch_plane_axis0(const T* X, const T* PX, const T* SX, const T* Trest, T*
     pa.X = X; pa.PX = PX; pa.SX = SX; pa.Trest = Trest; pa.exc = exc; pa.inc = inc;
     pa.n0 = n0; pa.MID = MID; pa.NY = NY; pa.NX = NX; pa.M = MID * NY * NX; pa.Q = Q;
     pa.k0 = (int)k0; pa.ky = (int)ky; pa.kx = (int)kx;
+    pa.nt = store_hint_ok(NX * (i64)sizeof(T));
     launch_plane_k0<T, Op, false>(pa, st);
 }
 
@@ -865,6 +872,7 @@ void launch_plane_weak(const T* X, T* inc, const T* wtot, T* wexc, i64 n0, i64 M
     pa.n0 = n0; pa.MID = MID; pa.NY = NY; pa.NX = NX; pa.M = MID * NY * NX;
     pa.Q = (n0 + k0 - 1) / k0;
     pa.k0 = (int)k0; pa.ky = (int)ky; pa.kx = (int)kx;
+    pa.nt = store_hint_ok(NX * (i64)sizeof(T));
     launch_plane_k0<T, Op, true>(pa, st);
 }
 

@@ -31,6 +31,7 @@ struct RowArgs {
     void* inc;          // (n0, NX) or null
     i64 n0, NX, Q;
     int k0, kx;
+    int nt;             // output stores carry the non-temporal hint
     i64 tiles, segblocks, nseg;
 };
 
@@ -120,7 +121,8 @@ __global__ void __launch_bounds__(256) k_row_axis0(RowArgs a) {
     T sx_raw = e;
     bool sx_valid = false;
 
-    auto block_step = [&](int q) __attribute__((always_inline)) {
+    auto block_step_h = [&](int q, auto ntc) __attribute__((always_inline)) {
+        constexpr bool NTS = decltype(ntc)::value;
         __syncthreads();
         T v[K0B];
 #pragma unroll
@@ -138,7 +140,7 @@ __global__ void __launch_bounds__(256) k_row_axis0(RowArgs a) {
 #pragma unroll
                 for (int r = K0B - 1; r >= 0; --r) {
                     S = Op::apply(v[r], S);
-                    bstore_nt<T>(ob, mb + (unsigned)r * row_bytes, Op::apply(tmp[r], S));
+                    bstore_h<T, NTS>(ob, mb + (unsigned)r * row_bytes, Op::apply(tmp[r], S));
                 }
             }
             if (do_inc) {
@@ -151,7 +153,7 @@ __global__ void __launch_bounds__(256) k_row_axis0(RowArgs a) {
                 for (int r = 0; r < K0B; ++r) {
                     T val = tmp[r];
                     if (r > 0) { p = Op::apply(p, v[r - 1]); val = Op::apply(val, p); }
-                    bstore_nt<T>(ob, mb + (unsigned)r * row_bytes, val);
+                    bstore_h<T, NTS>(ob, mb + (unsigned)r * row_bytes, val);
                 }
             }
         }
@@ -159,6 +161,10 @@ __global__ void __launch_bounds__(256) k_row_axis0(RowArgs a) {
 #pragma unroll
             for (int r = 0; r < K0B; ++r) w[r] = v[r];
         }
+    };
+    auto block_step = [&](int q) __attribute__((always_inline)) {
+        if (a.nt) block_step_h(q, std::true_type{});
+        else block_step_h(q, std::false_type{});
     };
     auto ring_fill_identity = [&](int from) {
         for (int r = from; r < K0B; ++r) ring[r * NT + tid] = e;
@@ -288,6 +294,7 @@ void launch_row_axis0(const T* X, const T* PX, const T* SX, const T* Trest, T* e
     RowArgs ra{};
     ra.X = X; ra.PX = PX; ra.SX = SX; ra.Trest = Trest; ra.exc = exc; ra.inc = inc;
     ra.n0 = n0; ra.NX = NX; ra.Q = Q; ra.k0 = (int)k0; ra.kx = (int)kx;
+    ra.nt = store_hint_ok(NX * (i64)sizeof(T));
     if (k0 <= 4) launch_row_kp<T, Op, 4>(ra, st);
     else if (k0 <= 8) launch_row_kp<T, Op, 8>(ra, st);
     else launch_row_kp<T, Op, 16>(ra, st);
