@@ -21,6 +21,7 @@
 // path that is not such a cache is neither used nor overwritten.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstdio>
 #include <cstring>
@@ -280,7 +281,8 @@ static exs_status plan_any(const exs_job* job, Arena& ar, std::vector<Rec>* out,
 }
 
 struct Launch {
-    int dtype, op, kind, kb;
+    int es, kind, kb;  // element size, step kind, register bucket
+    WlParts parts;     // (type, operator) parts: codes and chunk ranges
     size_t first;  // index of the first step in the device array
     int nsteps;
     size_t table;  // offset of its chunk table (task table for row tasks)
@@ -340,16 +342,23 @@ static exs_status build(exs_batch* b, void* ws, const TuneCfg& cfg) {
     b->phases.assign(maxlen, {});
     b->items = 0;
     for (size_t p = 0; p < maxlen; ++p) {
-        std::map<std::tuple<int, int, int, int>, std::vector<const Rec*>> groups;
+        // one launch per (element size, kind, register bucket): the steps
+        // carry their element type and operator
+        std::map<std::tuple<int, int, int>, std::vector<const Rec*>> groups;
         for (auto& r : recs)
             if (p < r.size())
-                groups[std::make_tuple(r[p].dtype, r[p].op, r[p].s.kind, r[p].kb)].push_back(&r[p]);
+                groups[std::make_tuple((int)dtype_size(r[p].dtype), r[p].s.kind, r[p].kb)]
+                    .push_back(&r[p]);
         for (auto& g : groups) {
+            // parts of one (type, operator) each, in code order
+            std::stable_sort(g.second.begin(), g.second.end(), [](const Rec* a, const Rec* b) {
+                return a->dtype * 4 + a->op < b->dtype * 4 + b->op;
+            });
             Launch L;
-            L.dtype = std::get<0>(g.first);
-            L.op = std::get<1>(g.first);
-            L.kind = std::get<2>(g.first);
-            L.kb = std::get<3>(g.first);
+            L.es = std::get<0>(g.first);
+            L.kind = std::get<1>(g.first);
+            L.kb = std::get<2>(g.first);
+            L.parts = WlParts{};
             L.first = all.size();
             L.nsteps = (int)g.second.size();
             L.table = table.size();
@@ -360,6 +369,15 @@ static exs_status build(exs_batch* b, void* ws, const TuneCfg& cfg) {
             L.lds = 0;
             for (const Rec* r : g.second) {
                 Step s = r->s;
+                const int code = r->dtype * 4 + r->op;
+                WlParts& P = L.parts;
+                if (P.n == 0 || P.code[P.n - 1] != code) {
+                    if (P.n == WL_MAX_PARTS)
+                        return set_error(EXS_EINVAL, "too many (type, operator) parts in a launch");
+                    P.code[P.n] = code;
+                    P.unit0[P.n] = rows ? tb : tb / WL_CHUNK;
+                    ++P.n;
+                }
                 s.task_begin = tb;
                 const i64 span = rows ? s.ntasks : (s.ntasks + WL_CHUNK - 1) / WL_CHUNK * WL_CHUNK;
                 tb += span;
@@ -368,9 +386,10 @@ static exs_status build(exs_batch* b, void* ws, const TuneCfg& cfg) {
                 all.push_back(s);
                 if (rows)
                     L.lds = std::max(L.lds, (size_t)rows_per_task(s.k) * rows_pitch(s.cb, s.k) *
-                                                dtype_size(L.dtype));
+                                                (size_t)L.es);
             }
             L.units = rows ? tb : tb / WL_CHUNK;
+            L.parts.unit0[L.parts.n] = L.units;
             b->items += (i64)g.second.size();
             b->phases[p].push_back(L);
         }
@@ -413,8 +432,19 @@ static void enqueue(exs_batch* b, const TuneCfg& cfg, hipStream_t st) {
             i64 g = L.kind == SK_BDBSR ? (L.units < 4 * cap ? L.units : 4 * cap)
                                        : (L.units < cap ? L.units : cap);
             if (g < 1) g = 1;
-            launch_worklist(L.dtype, L.op, L.kind, L.kb, b->dev_steps + L.first,
-                            b->dev_table + L.table, L.units, (int)g, L.lds, st);
+            // the workgroups split over the parts by their chunk counts (at
+            // least one each, never more than a part has chunks)
+            WlParts& P = L.parts;
+            P.wg0[0] = 0;
+            for (int i = 0; i < P.n; ++i) {
+                const i64 u = P.unit0[i + 1] - P.unit0[i];
+                i64 w = L.units > 0 ? g * u / L.units : 1;
+                if (w < 1) w = 1;
+                if (w > u && u > 0) w = u;
+                P.wg0[i + 1] = P.wg0[i] + (int)w;
+            }
+            launch_worklist(L.es, L.kind, L.kb, b->dev_steps + L.first, b->dev_table + L.table, P,
+                            L.lds, st);
         }
 }
 

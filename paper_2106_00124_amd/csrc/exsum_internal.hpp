@@ -52,10 +52,21 @@ inline int bucket_for(i64 k) {
 // work-list launch of the batched form (exsum_worklist.hip): `steps` is a
 // device array of Step (exsum_tasks.hpp) whose tasks start at multiples of
 // WL_CHUNK; `table` names the step of each of the `units` chunks (of each
-// task, for the row kind SK_BDBSR)
+// task, for the row kind SK_BDBSR).  One launch serves the steps of one kind
+// and register bucket over every element type of size `es` (4 or 8) and
+// every operator: its chunks are sorted by (type, operator) into up to six
+// parts, and each part gets its own share of the workgroups, so that a
+// workgroup runs the code of one type and operator only.
 constexpr int WL_CHUNK = 256;
-void launch_worklist(int dtype, int op, int kind, int kb, const void* steps, const int* table,
-                     i64 units, int grid, size_t lds, hipStream_t st);
+constexpr int WL_MAX_PARTS = 6;
+struct WlParts {
+    int n;                       // parts of the launch (1..WL_MAX_PARTS)
+    int code[WL_MAX_PARTS];      // dtype * 4 + op of each part (EXS_* codes)
+    i64 unit0[WL_MAX_PARTS + 1]; // first chunk (row task) of each part; unit0[n] = all
+    int wg0[WL_MAX_PARTS + 1];   // first workgroup of each part; wg0[n] = the grid
+};
+void launch_worklist(int es, int kind, int kb, const void* steps, const int* table,
+                     const WlParts& parts, size_t lds, hipStream_t st);
 
 // generic-path launchers (exsum_kernels.hip)
 template <typename T, class Op>

@@ -1073,4 +1073,35 @@ __device__ __forceinline__ void run_task(const Step& s, i64 i) {
         task_ex2<T, Op>((const T*)s.in0, (const T*)s.in3, (T*)s.out0, s.n, s.I, s.k, i);
 }
 
+// The element type and operator of a part of a work-list launch (uniform
+// over the workgroup, so the branch is a scalar one): F receives a value of
+// the type and the operator as template arguments.
+template <typename T, class Op>
+struct TypeOp {
+    using type = T;
+    using op = Op;
+};
+template <int ES, class F>
+__device__ __forceinline__ void with_type_op(int code, F&& f) {
+    if constexpr (ES == 4) {
+        switch (code) {
+            case EXS_F32 * 4 + EXS_SUM: f(TypeOp<float, OpSum>{}); break;
+            case EXS_F32 * 4 + EXS_MAX: f(TypeOp<float, OpMax>{}); break;
+            case EXS_F32 * 4 + EXS_MIN: f(TypeOp<float, OpMin>{}); break;
+            case EXS_I32 * 4 + EXS_SUM: f(TypeOp<int, OpSum>{}); break;
+            case EXS_I32 * 4 + EXS_MAX: f(TypeOp<int, OpMax>{}); break;
+            default: f(TypeOp<int, OpMin>{}); break;
+        }
+    } else {
+        switch (code) {
+            case EXS_F64 * 4 + EXS_SUM: f(TypeOp<double, OpSum>{}); break;
+            case EXS_F64 * 4 + EXS_MAX: f(TypeOp<double, OpMax>{}); break;
+            case EXS_F64 * 4 + EXS_MIN: f(TypeOp<double, OpMin>{}); break;
+            case EXS_I64 * 4 + EXS_SUM: f(TypeOp<long long, OpSum>{}); break;
+            case EXS_I64 * 4 + EXS_MAX: f(TypeOp<long long, OpMax>{}); break;
+            default: f(TypeOp<long long, OpMin>{}); break;
+        }
+    }
+}
+
 }  // namespace exs
