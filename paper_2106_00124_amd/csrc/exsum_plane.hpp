@@ -574,8 +574,13 @@ struct PlaneScanArgs {
 
 // FULL: exactly QMAX blocks and no middle axes (G == Ga), so every round is
 // full and known at compile time: the loads' wait counts are exact.
+// QMAX = 8 (short block axes: small tensors and their lower levels) with
+// boxes up to 8 asks for two workgroups per CU (at most 64 VGPRs; the LDS
+// fits twice), so that one workgroup's loads overlap the other's scans.
 template <typename T, class Op, int KP, int QMAX, bool FULL>
-__global__ void __launch_bounds__(1024) k_plane_scan(PlaneScanArgs a) {
+__global__ void __launch_bounds__(1024)
+__attribute__((amdgpu_waves_per_eu(QMAX == 8 && KP <= 8 ? 8 : 1)))
+k_plane_scan(PlaneScanArgs a) {
     using C = PlaneCfg<KP>;
     constexpr int NT = C::NT, P = C::P, SA = C::SA, SB = C::SB;
     static_assert(QMAX % (2 * P) == 0, "rounds come in pairs");
@@ -759,6 +764,9 @@ void launch_plane_scan_kp(PlaneScanArgs pa, hipStream_t st) {
     if (pa.Q == 32 && pa.G == pa.Ga)
         hipLaunchKernelGGL((k_plane_scan<T, Op, KP, 32, true>), dim3((unsigned)grid), dim3(C::NT),
                            0, st, pa);
+    else if (pa.Q <= 8)
+        hipLaunchKernelGGL((k_plane_scan<T, Op, KP, 8, false>), dim3((unsigned)grid),
+                           dim3(C::NT), 0, st, pa);
     else if (pa.Q <= 32)
         hipLaunchKernelGGL((k_plane_scan<T, Op, KP, 32, false>), dim3((unsigned)grid),
                            dim3(C::NT), 0, st, pa);
