@@ -199,8 +199,9 @@ struct EagerSink {
     void segtot(const T* Gw, const T* Ga, T* Tw, T* Ta, i64 Q, i64 M, i64 L) {
         launch_segtot<T, Op>(Gw, Ga, Tw, Ta, Q, M, L, st);
     }
-    void segexp(const T* Gw, const T* SPX, const T* SSX, T* PX, T* SX, i64 Q, i64 M, i64 L) {
-        launch_segexp<T, Op>(Gw, SPX, SSX, PX, SX, Q, M, L, st);
+    void segexp(const T* Gw, const T* SPX, const T* SSX, T* PX, T* SX, i64 Q, i64 M, i64 L,
+                i64 pxe) {
+        launch_segexp<T, Op>(Gw, SPX, SSX, PX, SX, Q, M, L, pxe, st);
     }
     // weak excluded sums need an inverse: numeric element types only
     void total(const T* X, i64 N, void* parts, T* tot) {
@@ -217,8 +218,8 @@ struct EagerSink {
     void ex1d_small(const T* R, T* exc, i64 n, i64 k) {
         launch_ex1d_small<T, Op>(R, exc, n, k, st);
     }
-    void blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M) {
-        launch_blockscan<T, Op>(Gw, Ga, PX, SX, R, Q, M, st);
+    void blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M, i64 pxe) {
+        launch_blockscan<T, Op>(Gw, Ga, PX, SX, R, Q, M, pxe, st);
     }
     void axis0(const T* W, const T* PX, const T* SX, const T* Trest, T* exc, T* inc, i64 n0,
                i64 M, i64 k0, i64 Q) {

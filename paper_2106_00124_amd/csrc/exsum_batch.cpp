@@ -150,7 +150,8 @@ struct ListSink {
         s.ntasks = ((Q + L - 1) / L) * M;
         push(s, 1);
     }
-    void segexp(const T* Gw, const T* SPX, const T* SSX, T* PX, T* SX, i64 Q, i64 M, i64 L) {
+    void segexp(const T* Gw, const T* SPX, const T* SSX, T* PX, T* SX, i64 Q, i64 M, i64 L,
+                i64) {
         Step s{};
         s.kind = SK_SEGEXP;
         s.in0 = Gw;
@@ -176,7 +177,9 @@ struct ListSink {
         s.ntasks = Q * M;
         push(s, 1);
     }
-    void blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M) {
+    // (pxe is 1 here: the fused levels, whose streams read PX at run starts
+    // only, are off)
+    void blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M, i64) {
         Step s{};
         s.kind = SK_SCAN;
         s.in0 = Gw;

@@ -95,7 +95,7 @@ template <typename T, class Op>
 void launch_segtot(const T* Gw, const T* Ga, T* Tw, T* Ta, i64 Q, i64 M, i64 L, hipStream_t st);
 template <typename T, class Op>
 void launch_segexp(const T* Gw, const T* SPX, const T* SSX, T* PX, T* SX, i64 Q, i64 M, i64 L,
-                   hipStream_t st);
+                   i64 pxe, hipStream_t st);
 // excluded sums of a 1-D tensor of at most 8192 elements in one workgroup
 bool ex1d_small_ok(i64 n);
 template <typename T, class Op>
@@ -107,8 +107,9 @@ void launch_blockagg(const T* X, T* Ga, i64 n0, i64 M, i64 k0, i64 Q, hipStream_
 template <typename T, class Op>
 void launch_aggmid(const T* A, T* X, T* Ga, T* G1, i64 n0, i64 P, i64 nf, i64 S, i64 k0, i64 kf,
                    i64 Q, hipStream_t st);
+// (PX stored for the blocks q with q % pxe == 0 only)
 template <typename T, class Op>
-void launch_blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M,
+void launch_blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M, i64 pxe,
                       hipStream_t st);
 template <typename T, class Op>
 void launch_axis0(const T* W, const T* PX, const T* SX, const T* Trest, T* exc, T* inc, i64 n0,

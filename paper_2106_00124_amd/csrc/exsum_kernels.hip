@@ -505,9 +505,9 @@ template <typename T, class Op>
 __global__ __launch_bounds__(256) void k_blockscan(const T* __restrict__ Gw,
                                                    const T* __restrict__ Ga,
                                                    T* __restrict__ PX, T* __restrict__ SX,
-                                                   T* __restrict__ R, i64 Q, i64 M) {
+                                                   T* __restrict__ R, i64 Q, i64 M, i64 pxe) {
     const i64 m = gtid();
-    if (m < M) task_scan<T, Op>(Gw, Ga, PX, SX, R, Q, M, m);
+    if (m < M) task_scan<T, Op>(Gw, Ga, PX, SX, R, Q, M, m, pxe);
 }
 
 template <typename T, class Op>
@@ -522,9 +522,10 @@ template <typename T, class Op>
 __global__ __launch_bounds__(256) void k_segexp(const T* __restrict__ Gw,
                                                 const T* __restrict__ SPX,
                                                 const T* __restrict__ SSX, T* __restrict__ PX,
-                                                T* __restrict__ SX, i64 Q, i64 M, i64 L) {
+                                                T* __restrict__ SX, i64 Q, i64 M, i64 L,
+                                                i64 pxe) {
     const i64 i = gtid();
-    if (i < ((Q + L - 1) / L) * M) task_segexp<T, Op>(Gw, SPX, SSX, PX, SX, Q, M, L, i);
+    if (i < ((Q + L - 1) / L) * M) task_segexp<T, Op>(Gw, SPX, SSX, PX, SX, Q, M, L, i, pxe);
 }
 
 template <typename T, class Op, int K0B, bool NARROW>
@@ -883,11 +884,11 @@ void launch_aggmid(const T* A, T* X, T* Ga, T* G1, i64 n0, i64 P, i64 nf, i64 S,
 }
 
 template <typename T, class Op>
-void launch_blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M,
+void launch_blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M, i64 pxe,
                       hipStream_t st) {
     KTimer timer("k_blockscan", st);
     hipLaunchKernelGGL((k_blockscan<T, Op>), dim3(grid_for(M)), dim3(256), 0, st, Gw, Ga, PX,
-                       SX, R, Q, M);
+                       SX, R, Q, M, pxe < 1 ? (i64)1 : pxe);
 }
 
 template <typename T, class Op>
@@ -899,10 +900,10 @@ void launch_segtot(const T* Gw, const T* Ga, T* Tw, T* Ta, i64 Q, i64 M, i64 L, 
 
 template <typename T, class Op>
 void launch_segexp(const T* Gw, const T* SPX, const T* SSX, T* PX, T* SX, i64 Q, i64 M, i64 L,
-                   hipStream_t st) {
+                   i64 pxe, hipStream_t st) {
     KTimer timer("k_segexp", st);
     hipLaunchKernelGGL((k_segexp<T, Op>), dim3(grid_for(((Q + L - 1) / L) * M)), dim3(256), 0, st,
-                       Gw, SPX, SSX, PX, SX, Q, M, L);
+                       Gw, SPX, SSX, PX, SX, Q, M, L, pxe < 1 ? (i64)1 : pxe);
 }
 
 template <typename T, class Op>
@@ -979,12 +980,12 @@ void launch_fill(void* out, i64 count, int dtype, int kind, uint64_t seed, i64 l
     template void launch_ex1d_small<T, OP>(const T*, T*, i64, i64, hipStream_t);               \
     template void launch_segtot<T, OP>(const T*, const T*, T*, T*, i64, i64, i64, hipStream_t); \
     template void launch_segexp<T, OP>(const T*, const T*, const T*, T*, T*, i64, i64, i64,     \
-                                       hipStream_t);                                           \
+                                       i64, hipStream_t);                                      \
     template void launch_bdbs<T, OP>(const T*, T*, i64, i64, i64, i64, hipStream_t);           \
     template void launch_blockagg<T, OP>(const T*, T*, i64, i64, i64, i64, hipStream_t);       \
     template void launch_aggmid<T, OP>(const T*, T*, T*, T*, i64, i64, i64, i64, i64, i64, i64,  \
                                        hipStream_t);                                           \
-    template void launch_blockscan<T, OP>(const T*, const T*, T*, T*, T*, i64, i64,            \
+    template void launch_blockscan<T, OP>(const T*, const T*, T*, T*, T*, i64, i64, i64,       \
                                           hipStream_t);                                        \
     template void launch_axis0<T, OP>(const T*, const T*, const T*, const T*, T*, T*, i64, i64, \
                                       i64, i64, hipStream_t);

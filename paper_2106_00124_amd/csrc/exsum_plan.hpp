@@ -103,12 +103,14 @@ static const T* filter_axes(const T* src, const i64* n, const i64* k, int d, int
 // or the walk is short, the blocks are cut into segments of L, the segment
 // totals are scanned the same way (recursively), and the segments are
 // expanded in parallel.
+// PX is stored only for blocks q % pxe == 0 (the run starts of a fused
+// stream); the scan of the segment totals stores all of its own.
 template <typename T, class Sink>
 static void emit_blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M, Arena& ar,
-                           bool dry, Sink& sink) {
+                           bool dry, Sink& sink, i64 pxe = 1) {
     constexpr i64 L = 64;
     if (M >= ((i64)1 << 18) || Q <= L) {
-        if (!dry) sink.blockscan(Gw, Ga, PX, SX, R, Q, M);
+        if (!dry) sink.blockscan(Gw, Ga, PX, SX, R, Q, M, pxe);
         return;
     }
     const i64 S = (Q + L - 1) / L;
@@ -118,7 +120,7 @@ static void emit_blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, 
     T* SSX = ar.take<T>(S * M);
     if (!dry) sink.segtot(Gw, Ga, Tw, Ta, Q, M, L);
     emit_blockscan<T>(Tw, Ta, SPX, SSX, R, S, M, ar, dry, sink);
-    if (!dry) sink.segexp(Gw, SPX, SSX, PX, SX, Q, M, L);
+    if (!dry) sink.segexp(Gw, SPX, SSX, PX, SX, Q, M, L, pxe);
 }
 
 template <typename T, class Sink>
@@ -355,7 +357,11 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
         } else {
             Gw = filter_axes<T>(Ga, gn, gk, dj, 1, dj - 1, gb0, gb1, dry, sink);
         }
-        emit_blockscan<T>(Gw, Ga, PX[j], SX[j], R[j + 1], Q[j], M[j], ar, dry, sink);
+        // a fused level's stream reads the block prefix only where its runs start
+        emit_blockscan<T>(Gw, Ga, PX[j], SX[j], R[j + 1], Q[j], M[j], ar, dry, sink,
+                          fz[j] ? plane_axis0_run_blocks(Q[j], mid, n[d - 2], n[d - 1],
+                                                         k[d - 2], k[d - 1])
+                                : 1);
     }
     // bottom-up: stream the first axis of each level, adding the level below
     for (int j = d - 1; j >= 0; --j) {

@@ -123,15 +123,19 @@ __device__ __forceinline__ void task_agg(const T* __restrict__ X, T* __restrict_
 
 // Per point m (= task): PX[q] = op of Gw[q'] for q' < q, SX[q] = op of Gw[q']
 // for q' > q, R[m] = op over all blocks of Ga (the reduction of axis 0).
+// PX is stored for the blocks q with q % pxe == 0 only (where the runs of the
+// axis-0 stream that reads it start).
 template <typename T, class Op>
 __device__ __forceinline__ void task_scan(const T* __restrict__ Gw, const T* __restrict__ Ga,
                                           T* __restrict__ PX, T* __restrict__ SX,
-                                          T* __restrict__ R, i64 Q, i64 M, i64 m) {
+                                          T* __restrict__ R, i64 Q, i64 M, i64 m, i64 pxe = 1) {
     const T e = Op::template id<T>();
     T p = e, r = e;
+    i64 c = 0;
 #pragma unroll 8
     for (i64 q = 0; q < Q; ++q) {
-        PX[q * M + m] = p;
+        if (c == 0) PX[q * M + m] = p;
+        c = c + 1 == pxe ? 0 : c + 1;
         p = Op::apply(p, Gw[q * M + m]);
         r = Op::apply(r, Ga[q * M + m]);
     }
@@ -170,13 +174,17 @@ __device__ __forceinline__ void task_segtot(const T* __restrict__ Gw, const T* _
 template <typename T, class Op>
 __device__ __forceinline__ void task_segexp(const T* __restrict__ Gw, const T* __restrict__ SPX,
                                             const T* __restrict__ SSX, T* __restrict__ PX,
-                                            T* __restrict__ SX, i64 Q, i64 M, i64 L, i64 idx) {
+                                            T* __restrict__ SX, i64 Q, i64 M, i64 L, i64 idx,
+                                            i64 pxe = 1) {
     const i64 m = idx % M, sg = idx / M;
     const i64 q0 = sg * L, q1 = q0 + L < Q ? q0 + L : Q;
     T p = SPX[idx];
+    // PX only for blocks q % pxe == 0 (as in task_scan)
+    i64 c = q0 % pxe;
 #pragma unroll 8
     for (i64 q = q0; q < q1; ++q) {
-        PX[q * M + m] = p;
+        if (c == 0) PX[q * M + m] = p;
+        c = c + 1 == pxe ? 0 : c + 1;
         p = Op::apply(p, Gw[q * M + m]);
     }
     T s = SSX[idx];

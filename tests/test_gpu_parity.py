@@ -271,3 +271,27 @@ def test_parity_axis0_one_output(orc, mode, shape, box, dtype, op):
     a = make_input(shape, dtype, seed=seed, op=op)
     inc, exc = gpu_run(a, box, op, mode)
     compare_full(orc, a, box, op, dtype, inc, exc, what=f"{shape} {box} {dtype} {op} {mode}")
+
+
+# fused levels with more than 64 blocks along axis 0: the trailing-axes pass,
+# then the block scans, which store the block prefix only where the stream's
+# runs start; at least 2^18 points take the direct scan, fewer the segmented
+# one (a ragged last block and segment, boxes of different buckets on the
+# trailing axes)
+TWO_PASS = [
+    ((141, 512, 520), (2, 5, 3)),
+    ((133, 520, 512), (2, 3, 16)),
+    ((301, 100, 120), (2, 5, 7)),
+    ((1030, 64, 40), (4, 3, 16)),
+]
+
+
+@pytest.mark.parametrize("shape,box", TWO_PASS, ids=lambda v: "x".join(map(str, v)))
+@pytest.mark.parametrize("dtype,op", [("i32", "sum"), ("f32", "max"), ("f32", "sum")],
+                         ids=lambda v: str(v))
+def test_parity_fused_two_pass_scan(orc, shape, box, dtype, op):
+    seed = seed_of(shape, box, dtype, op, "twopass")
+    say(f"[two-pass] shape={shape} box={box} dtype={dtype} op={op} seed={seed}")
+    a = make_input(shape, dtype, seed=seed, op=op)
+    inc, exc = gpu_run(a, box, op, "both")
+    compare_full(orc, a, box, op, dtype, inc, exc, what=f"two-pass {shape} {box}")
