@@ -357,11 +357,14 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
         } else {
             Gw = filter_axes<T>(Ga, gn, gk, dj, 1, dj - 1, gb0, gb1, dry, sink);
         }
-        // a fused level's stream reads the block prefix only where its runs start
-        emit_blockscan<T>(Gw, Ga, PX[j], SX[j], R[j + 1], Q[j], M[j], ar, dry, sink,
-                          fz[j] ? plane_axis0_run_blocks(Q[j], mid, n[d - 2], n[d - 1],
-                                                         k[d - 2], k[d - 1])
-                                : 1);
+        // the fused streams (of a level of rank >= 3, or of a 2-D level) read
+        // the block prefix only where their runs start
+        const i64 pxe = fz[j] ? plane_axis0_run_blocks(Q[j], mid, n[d - 2], n[d - 1], k[d - 2],
+                                                       k[d - 1])
+                        : dj == 2 && sink.row_ok(n[j], n[j + 1], k[j], k[j + 1])
+                            ? row_axis0_run_blocks(Q[j], n[j + 1], k[j + 1])
+                            : 1;
+        emit_blockscan<T>(Gw, Ga, PX[j], SX[j], R[j + 1], Q[j], M[j], ar, dry, sink, pxe);
     }
     // bottom-up: stream the first axis of each level, adding the level below
     for (int j = d - 1; j >= 0; --j) {

@@ -273,8 +273,8 @@ def test_parity_axis0_one_output(orc, mode, shape, box, dtype, op):
     compare_full(orc, a, box, op, dtype, inc, exc, what=f"{shape} {box} {dtype} {op} {mode}")
 
 
-# fused levels with more than 64 blocks along axis 0: the trailing-axes pass,
-# then the block scans, which store the block prefix only where the stream's
+# fused levels with more than 64 blocks along axis 0: the trailing-axes pass
+# (or the row pass of a 2-D level), then the block scans, which store the block prefix only where the stream's
 # runs start; at least 2^18 points take the direct scan, fewer the segmented
 # one (a ragged last block and segment, boxes of different buckets on the
 # trailing axes)
@@ -283,6 +283,9 @@ TWO_PASS = [
     ((133, 520, 512), (2, 3, 16)),
     ((301, 100, 120), (2, 5, 7)),
     ((1030, 64, 40), (4, 3, 16)),
+    # 2-D levels streamed by the fused row kernel
+    ((2001, 300), (8, 5)),
+    ((141, 262150), (2, 7)),
 ]
 
 
