@@ -176,6 +176,17 @@ struct EagerSink {
         launch_aggmid<T, Op>(A, X, Ga, G1, n0, P, nf, S, k0, kf, Q, st);
     }
     bool small1d_ok(i64 n) const { return ex1d_small_ok(n); }
+    // the one-workgroup rank-2 kernel: numeric types under +, max and min
+    static constexpr bool kSmall2d =
+        std::is_arithmetic<T>::value &&
+        (std::is_same<Op, OpSum>::value || std::is_same<Op, OpMax>::value ||
+         std::is_same<Op, OpMin>::value);
+    bool small2d_ok(i64 n0, i64 n1, i64 k0, i64 k1) const {
+        return kSmall2d && small2d_eligible(n0, n1, k0, k1, (int)sizeof(T));
+    }
+    void small2d(const T* A, T* exc, T* inc, i64 n0, i64 n1, i64 k0, i64 k1) {
+        if constexpr (kSmall2d) launch_small2d<T, Op>(A, exc, inc, n0, n1, k0, k1, st);
+    }
     i64 tail_box_max() const { return tail_box_max_elems((int)sizeof(T)); }
     void bdbs_tail(const T* in, T* out, i64 O, int m, const i64* n, const i64* k) {
         launch_bdbs_tail<T, Op>(in, out, O, m, n, k, st);

@@ -62,6 +62,9 @@ struct ListSink {
     void row_axis0(const T*, const T*, const T*, const T*, T*, T*, i64, i64, i64, i64, i64) {}
     // the single-workgroup kernel for a short last level has no work-list form
     bool small1d_ok(i64) const { return false; }
+    // nor the one-workgroup rank-2 kernel
+    bool small2d_ok(i64, i64, i64, i64) const { return false; }
+    void small2d(const T*, T*, T*, i64, i64, i64, i64) {}
     // the fused levels are off here, and with them the fused aggregate pass
     bool aggmid_ok() const { return false; }
     void aggmid(const T*, T*, T*, T*, i64, i64, i64, i64, i64, i64, i64) {}

@@ -98,6 +98,14 @@ void launch_segexp(const T* Gw, const T* SPX, const T* SSX, T* PX, T* SX, i64 Q,
                    i64 pxe, hipStream_t st);
 // excluded sums of a 1-D tensor of at most 8192 elements in one workgroup
 bool ex1d_small_ok(i64 n);
+// both levels of a small rank-2 tensor in one workgroup (exsum_small2d.hip):
+// at most SMALL2D_MAX_N0 x SMALL2D_MAX_N1 elements and SMALL2D_BYTES bytes,
+// boxes along axis 1 of at most SMALL2D_MAX_K1
+constexpr int SMALL2D_BYTES = 32768, SMALL2D_MAX_N0 = 128, SMALL2D_MAX_N1 = 1024,
+              SMALL2D_MAX_K1 = 64;
+bool small2d_eligible(i64 n0, i64 n1, i64 k0, i64 k1, int es);
+template <typename T, class Op>
+void launch_small2d(const T* A, T* exc, T* inc, i64 n0, i64 n1, i64 k0, i64 k1, hipStream_t st);
 template <typename T, class Op>
 void launch_ex1d_small(const T* R, T* exc, i64 n, i64 k, hipStream_t st);
 template <typename T, class Op>

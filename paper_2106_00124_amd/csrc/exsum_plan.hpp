@@ -135,6 +135,11 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
     const bool want_exc = (job->mode & EXS_EXCLUDED) && !weak;  // strong excluded sums
     const bool dry = ar.dry;
     const i64 N = prod(n, 0, d);
+    // a small rank-2 tensor: both levels in one workgroup, no workspace
+    if (d == 2 && !weak && sink.small2d_ok(n[0], n[1], k[0], k[1])) {
+        if (!dry) sink.small2d(A, exc, inc, n[0], n[1], k[0], k[1]);
+        return EXS_OK;
+    }
     // a level of rank >= 3 streams its first axis with the fused plane kernel
     // when it applies; it box-sums the two trailing axes itself, the middle
     // axes are done first (levels past 0 exist only for strong excluded sums)

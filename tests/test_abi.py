@@ -119,7 +119,8 @@ def test_run_rejects_null_and_aliasing_on_host():
     j = _lib.make_job(2, 0, 0, 2, [8, 8], [2, 2], 0x1000, None, 0x1080)
     assert L.exs_run(ctypes.byref(j), None, 0, None) == 1          # overlaps input
     assert b"overlaps" in L.exs_last_error()
-    j = _lib.make_job(2, 0, 0, 2, [8, 8], [2, 2], 0x1000, None, 0x9000)
+    # (a shape past the one-workgroup rank-2 kernel, which needs no workspace)
+    j = _lib.make_job(2, 0, 0, 2, [300, 300], [2, 2], 0x1000, None, 0x100000)
     assert L.exs_run(ctypes.byref(j), None, 0, None) == 3          # workspace too small
     j = _lib.make_job(2, 0, 0, 2, [8, 8], [2, 2], 0x1002, None, 0x9000)
     assert L.exs_run(ctypes.byref(j), None, 0, None) == 1          # misaligned input

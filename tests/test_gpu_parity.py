@@ -298,3 +298,32 @@ def test_parity_fused_two_pass_scan(orc, shape, box, dtype, op):
     a = make_input(shape, dtype, seed=seed, op=op)
     inc, exc = gpu_run(a, box, op, "both")
     compare_full(orc, a, box, op, dtype, inc, exc, what=f"two-pass {shape} {box}")
+
+
+# rank-2 tensors small enough for the one-workgroup kernel (at most 128 rows,
+# 1024 columns, 32 KiB, boxes of at most 64 along axis 1) and just past each of
+# its limits (the general chain of launches): both outputs and each alone
+SMALL2D = [
+    ((1, 1), (1, 1)),
+    ((1, 1024), (1, 64)),
+    ((8, 1024), (3, 17)),
+    ((128, 64), (128, 64)),
+    ((128, 64), (5, 1)),
+    ((127, 33), (10, 7)),
+    ((129, 2), (4, 2)),
+    ((100, 90), (9, 65)),
+    ((2, 1025), (2, 3)),
+]
+
+
+@pytest.mark.parametrize("shape,box", SMALL2D, ids=lambda v: "x".join(map(str, v)))
+@pytest.mark.parametrize("dtype,op", [("f32", "sum"), ("f64", "sum"), ("i32", "max"),
+                                      ("i64", "min"), ("f32", "max")], ids=lambda v: str(v))
+@pytest.mark.parametrize("mode", ["both", "inc", "exc"])
+def test_parity_small2d(orc, shape, box, dtype, op, mode):
+    seed = seed_of(shape, box, dtype, op, mode, "small2d")
+    say(f"[small2d] shape={shape} box={box} dtype={dtype} op={op} mode={mode} seed={seed}")
+    a = make_input(shape, dtype, seed=seed, op=op)
+    inc, exc = gpu_run(a, box, op, mode)
+    compare_full(orc, a, box, op, dtype, inc if mode != "exc" else None,
+                 exc if mode != "inc" else None, what=f"small2d {shape} {box} {mode}")
