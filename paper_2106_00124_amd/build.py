@@ -9,8 +9,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libexsum.so")
 
-SOURCES = ["exsum_kernels.hip", "exsum_plane_f32.hip", "exsum_plane_i32.hip", "exsum_row.hip", "exsum_ex1d.hip", "exsum_tailbox.hip", "exsum_corners.hip", "exsum_small2d.hip",
-           "exsum_worklist.hip", "exsum_api.cpp", "exsum_batch.cpp", "exsum_server.cpp"]
+# longest compiles first, so that they run side by side
+SOURCES = ["exsum_worklist.hip", "exsum_kernels.hip", "exsum_plane_f32.hip", "exsum_plane_i32.hip",
+           "exsum_row.hip", "exsum_ex1d.hip", "exsum_tailbox.hip", "exsum_corners.hip",
+           "exsum_small2d.hip", "exsum_api.cpp", "exsum_batch.cpp", "exsum_server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
