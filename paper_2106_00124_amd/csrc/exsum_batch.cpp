@@ -78,7 +78,12 @@ struct ListSink {
     void total(const T*, i64, void*, T*) {}
     void weak_exc(const T*, const T*, T*, i64) {}
     void plane_weak(const T*, T*, const T*, T*, i64, i64, i64, i64, i64, i64, i64) {}
-    void push(const Step& s, int kb) { out->push_back(Rec{s, dtype, op, kb}); }
+    // 4-byte generic BDBS and axis-0 steps with boxes up to 8 share the
+    // bucket of 8 (every such kernel runs at full occupancy): fewer launches
+    void push(const Step& s, int kb) {
+        if (sizeof(T) == 4 && (s.kind == SK_BDBS || s.kind == SK_AX0) && kb < 8) kb = 8;
+        out->push_back(Rec{s, dtype, op, kb});
+    }
     void bdbs(const T* in, T* o, i64 O, i64 n, i64 I, i64 k) {
         Step s{};
         s.k = (int)k;
