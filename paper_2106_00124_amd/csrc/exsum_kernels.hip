@@ -655,7 +655,10 @@ void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st
                                st, in, out, O, n, I, (int)k, cb, tasks);
         return;
     }
-    i64 nchunks = (65536 + cols - 1) / cols;
+    // chunks of blocks per column: tasks for 32 wavefronts per CU when the
+    // columns are few, 16 when they are many (as for the axis-0 stream)
+    const i64 want = cols <= ((i64)1 << 16) ? ((i64)1 << 19) : ((i64)1 << 18);
+    i64 nchunks = (want + cols - 1) / cols;
     if (nchunks > nb) nchunks = nb;
     if (nchunks < 1) nchunks = 1;
     const i64 cb = (nb + nchunks - 1) / nchunks;
@@ -942,7 +945,11 @@ void launch_axis0(const T* W, const T* PX, const T* SX, const T* Trest, T* exc, 
 #undef EXS_AX0C
         return;
     }
-    i64 nseg = (65536 + M - 1) / M;
+    // runs of blocks per point: enough tasks for 32 wavefronts per CU when
+    // the points are few (the stream is latency-bound with fewer), 16 when
+    // they are many (each run rereads one block)
+    const i64 want = M <= ((i64)1 << 16) ? ((i64)1 << 19) : ((i64)1 << 18);
+    i64 nseg = (want + M - 1) / M;
     if (nseg > Q) nseg = Q;
     if (nseg < 1) nseg = 1;
     const i64 segblocks = (Q + nseg - 1) / nseg;
