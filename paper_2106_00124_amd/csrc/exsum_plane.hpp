@@ -48,7 +48,7 @@ struct PlaneArgs {
 };
 
 // 32 x 32 blocked points per workgroup, one thread each; P planes per round.
-template <int KP>
+template <int KP, int PLANES = 4>
 struct PlaneCfg {
     static constexpr int NT = 1024;
     static constexpr int TYM = 32, TXM = 32;
@@ -61,7 +61,7 @@ struct PlaneCfg {
     // real halo elements of a tile: NB blocks of k <= KP points and k - 1 more
     static constexpr int MAXIN = (TYM + KP - 1) * (TXM + KP - 1);
     static constexpr int NLOAD = (MAXIN + NT - 1) / NT;
-    static constexpr int P = 4;
+    static constexpr int P = PLANES;
     static constexpr int RT = (P * ROWS * NBX + NT - 1) / NT;  // row tasks per thread
     static constexpr int CT = (P * TXM * NBY + NT - 1) / NT;   // column tasks per thread
 };
@@ -127,13 +127,13 @@ __device__ __forceinline__ void bdbs_block(const T* __restrict__ src, T* __restr
 // multiple of k0) and K0B / P is even, so each block is a fixed sequence of
 // full rounds; otherwise rounds are sized at run time.
 // WEAK: also store total - included (the weak excluded sum, + only).
-// K0B = 4 with boxes up to 8 fits in 64 VGPRs and half the LDS: two
-// workgroups per CU, so that one workgroup's loads overlap the other's
-// scans on the short streams these small boxes take.
+// K0B <= 8 with boxes up to 8 fits in 64 VGPRs and half the LDS (K0B = 8
+// with two planes per round instead of four): two workgroups per CU, so that
+// one workgroup's loads overlap the other's scans.
 template <typename T, class Op, int K0B, int KP, bool WHOLE, bool WEAK>
 __global__ void __launch_bounds__(1024)
-__attribute__((amdgpu_waves_per_eu(K0B == 4 && KP <= 8 ? 8 : 1))) k_plane_axis0(PlaneArgs a) {
-    using C = PlaneCfg<KP>;
+__attribute__((amdgpu_waves_per_eu(K0B <= 8 && KP <= 8 ? 8 : 1))) k_plane_axis0(PlaneArgs a) {
+    using C = PlaneCfg<KP, K0B == 8 && KP <= 8 ? 2 : 4>;
     constexpr int NT = C::NT, P = C::P, SA = C::SA, SB = C::SB;
     __shared__ T sA[P * SA + 1];  // + a dummy word for writes that must land nowhere
     __shared__ T sB[P * SB];
