@@ -561,7 +561,7 @@ __global__ void __launch_bounds__(1024) k_plane_bdbs(Plane2Args a) {
 // block axis q without storing them:
 //   PX[q, m] = op of Gw[q', m] for q' < q,  SX[q, m] = op of Gw[q', m] for q' > q,
 //   R[m]     = op of Ga[q, m] over all q (the reduction that feeds the next level).
-// One workgroup owns a tile for all Q <= QMAX planes (QMAX = 32 or 64); the
+// One workgroup owns a tile for all Q <= QMAX planes (QMAX = 8 to 64); the
 // box-summed values of its points stay in registers.
 // ---------------------------------------------------------------------------
 struct PlaneScanArgs {
@@ -579,12 +579,12 @@ struct PlaneScanArgs {
 
 // FULL: exactly QMAX blocks and no middle axes (G == Ga), so every round is
 // full and known at compile time: the loads' wait counts are exact.
-// QMAX = 8 (short block axes: small tensors and their lower levels) with
-// boxes up to 8 asks for two workgroups per CU (at most 64 VGPRs; the LDS
-// fits twice), so that one workgroup's loads overlap the other's scans.
+// QMAX = 8 or 16 (short block axes: small tensors and their lower levels)
+// with boxes up to 8 asks for two workgroups per CU (at most 64 VGPRs; the
+// LDS fits twice), so that one workgroup's loads overlap the other's scans.
 template <typename T, class Op, int KP, int QMAX, bool FULL>
 __global__ void __launch_bounds__(1024)
-__attribute__((amdgpu_waves_per_eu(QMAX == 8 && KP <= 8 ? 8 : 1)))
+__attribute__((amdgpu_waves_per_eu(QMAX <= 16 && KP <= 8 ? 8 : 1)))
 k_plane_scan(PlaneScanArgs a) {
     using C = PlaneCfg<KP>;
     constexpr int NT = C::NT, P = C::P, SA = C::SA, SB = C::SB;
@@ -771,6 +771,9 @@ void launch_plane_scan_kp(PlaneScanArgs pa, hipStream_t st) {
                            0, st, pa);
     else if (pa.Q <= 8)
         hipLaunchKernelGGL((k_plane_scan<T, Op, KP, 8, false>), dim3((unsigned)grid),
+                           dim3(C::NT), 0, st, pa);
+    else if (pa.Q <= 16)
+        hipLaunchKernelGGL((k_plane_scan<T, Op, KP, 16, false>), dim3((unsigned)grid),
                            dim3(C::NT), 0, st, pa);
     else if (pa.Q <= 32)
         hipLaunchKernelGGL((k_plane_scan<T, Op, KP, 32, false>), dim3((unsigned)grid),
