@@ -233,8 +233,8 @@ struct EagerSink {
         launch_blockscan<T, Op>(Gw, Ga, PX, SX, R, Q, M, pxe, st);
     }
     void axis0(const T* W, const T* PX, const T* SX, const T* Trest, T* exc, T* inc, i64 n0,
-               i64 M, i64 k0, i64 Q) {
-        launch_axis0<T, Op>(W, PX, SX, Trest, exc, inc, n0, M, k0, Q, st);
+               i64 M, i64 k0, i64 Q, T* ex2t) {
+        launch_axis0<T, Op>(W, PX, SX, Trest, exc, inc, n0, M, k0, Q, ex2t, st);
     }
     // the fused kernels are built for 4-byte element types only
     void plane_axis0(const T* X, const T* PX, const T* SX, const T* Trest, T* exc, T* inc, i64 n0,

@@ -200,8 +200,10 @@ struct ListSink {
         s.ntasks = M;
         push(s, 1);
     }
+    // (ex2t, the chunk totals of the plain call's chunked long-box sweep, is
+    // not used: the work-list runs the per-column sweep)
     void axis0(const T* W, const T* PX, const T* SX, const T* Trest, T* exc, T* inc, i64 n0,
-               i64 M, i64 k0, i64 Q) {
+               i64 M, i64 k0, i64 Q, T*) {
         const int kb = bucket_for(k0);
         if (kb == 0) {
             if (exc) {

@@ -119,9 +119,20 @@ void launch_aggmid(const T* A, T* X, T* Ga, T* G1, i64 n0, i64 P, i64 nf, i64 S,
 template <typename T, class Op>
 void launch_blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M, i64 pxe,
                       hipStream_t st);
+// Boxes longer than 64 along an axis take per-column sweeps; with few columns
+// the sweeps go in chunks of rows (ex2_chunks: chunks per column, 1 for the
+// plain per-column sweep), the axis-0 stream's needing C x M chunk totals of
+// workspace (ex2t)
+inline i64 ex2_chunks(i64 n, i64 cols) {
+    if (cols >= ((i64)1 << 18)) return 1;
+    i64 c = (((i64)1 << 19) + cols - 1) / cols;
+    const i64 cmax = (n + 63) / 64;  // chunks of at least 64 rows
+    if (c > cmax) c = cmax;
+    return c < 1 ? 1 : c;
+}
 template <typename T, class Op>
 void launch_axis0(const T* W, const T* PX, const T* SX, const T* Trest, T* exc, T* inc, i64 n0,
-                  i64 M, i64 k0, i64 Q, hipStream_t st);
+                  i64 M, i64 k0, i64 Q, T* ex2t, hipStream_t st);
 template <typename T, class Op>
 void launch_plane_axis0(const T* X, const T* PX, const T* SX, const T* Trest, T* exc, T* inc,
                         i64 n0, i64 MID, i64 NY, i64 NX, i64 k0, i64 ky, i64 kx, i64 Q,

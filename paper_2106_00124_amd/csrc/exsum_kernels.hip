@@ -539,6 +539,109 @@ __global__ __launch_bounds__(256) void k_axis0(const T* __restrict__ W, const T*
         task_axis0<T, Op, K0B, NARROW>(W, PX, SX, Trest, exc, inc, n0, M, k0, Q, segblocks, idx);
 }
 
+
+// Boxes longer than 64 with few columns: the same sweeps in chunks of L rows,
+// one thread per (chunk, column).  Excluded part along axis 0: first the
+// chunk totals (Tc, chunk-major); then each thread writes, for its rows x,
+// the op of W from x + k0 on (a backward walk that starts from the totals of
+// the chunks after the one holding its highest row + k0 + 1, and that
+// chunk's rows above it), then adds the op of W before x (the lower-dimensional
+// term and the totals of the chunks before its own, then a forward walk).
+template <typename T, class Op>
+__global__ __launch_bounds__(256) void k_ex2c_tot(const T* __restrict__ W, T* __restrict__ Tc,
+                                                  i64 n0, i64 M, i64 L, i64 C) {
+    const i64 idx = gtid();
+    if (idx >= C * M) return;
+    const i64 m = idx % M, c = idx / M;
+    const i64 x0 = c * L, x1 = x0 + L < n0 ? x0 + L : n0;
+    T s = Op::template id<T>();
+    for (i64 x = x0; x < x1; ++x) s = Op::apply(s, W[x * M + m]);
+    Tc[idx] = s;
+}
+
+template <typename T, class Op>
+__global__ __launch_bounds__(256) void k_ex2c_out(const T* __restrict__ W,
+                                                  const T* __restrict__ Trest,
+                                                  const T* __restrict__ Tc, T* __restrict__ exc,
+                                                  i64 n0, i64 M, i64 k0, i64 L, i64 C) {
+    const i64 idx = gtid();
+    if (idx >= C * M) return;
+    const T e = Op::template id<T>();
+    const i64 m = idx % M, c = idx / M;
+    const i64 x0 = c * L, x1 = x0 + L < n0 ? x0 + L : n0;
+    // rows whose box reaches the end: nothing after it
+    for (i64 x = (n0 - k0 > x0 ? n0 - k0 : x0); x < x1; ++x) exc[x * M + m] = e;
+    if (x0 + k0 < n0) {
+        const i64 ytop = x1 - 1 + k0 < n0 - 1 ? x1 - 1 + k0 : n0 - 1;
+        const i64 yn = ytop + 1;
+        T s = e;
+        if (yn < n0) {
+            const i64 cc = yn / L;
+            for (i64 c2 = C - 1; c2 > cc; --c2) s = Op::apply(Tc[c2 * M + m], s);
+            const i64 ye = (cc + 1) * L < n0 ? (cc + 1) * L : n0;
+            for (i64 y = ye - 1; y >= yn; --y) s = Op::apply(W[y * M + m], s);
+        }
+        for (i64 y = ytop; y >= x0 + k0; --y) {
+            s = Op::apply(W[y * M + m], s);
+            exc[(y - k0) * M + m] = s;
+        }
+    }
+    T p = Trest ? Trest[m] : e;
+    for (i64 c2 = 0; c2 < c; ++c2) p = Op::apply(p, Tc[c2 * M + m]);
+    for (i64 x = x0; x < x1; ++x) {
+        exc[x * M + m] = Op::apply(p, exc[x * M + m]);
+        p = Op::apply(p, W[x * M + m]);
+    }
+}
+
+// BDBS for boxes longer than 64 along an axis of an (O, n, I) tensor in chunks
+// of L rows: thread (o, chunk, i) forms the range suffixes of its rows (a
+// backward walk from the end of the block holding its last row), then adds
+// the range prefix of the next block up to x + k - 1 (a forward walk from the
+// start of the block holding its first row + k - 1), and for the windows
+// whose next block is the partial last block, that block's whole op.
+template <typename T, class Op>
+__global__ __launch_bounds__(256) void k_bdbs2c(const T* __restrict__ in, T* __restrict__ out,
+                                                i64 O, i64 n, i64 I, i64 k, i64 L, i64 C) {
+    const i64 idx = gtid();
+    if (idx >= O * C * I) return;
+    const T e = Op::template id<T>();
+    const i64 i = idx % I, rest = idx / I;
+    const i64 c = rest % C, o = rest / C;
+    const T* src = in + o * n * I + i;
+    T* dst = out + o * n * I + i;
+    const i64 x0 = c * L, x1 = x0 + L < n ? x0 + L : n;
+    if (x0 >= x1) return;
+    const i64 bend = ((x1 - 1) / k + 1) * k < n ? ((x1 - 1) / k + 1) * k : n;
+    T rs = e;
+    for (i64 y = bend - 1; y >= x0; --y) {
+        const bool last = (y % k == k - 1) || (y == n - 1);
+        rs = last ? src[y * I] : Op::apply(src[y * I], rs);
+        if (y < x1) dst[y * I] = rs;
+    }
+    const i64 ylo = x0 + k - 1;
+    const i64 yhi = x1 - 1 + k - 1 < n - 1 ? x1 - 1 + k - 1 : n - 1;
+    if (ylo <= yhi) {
+        T rp = e;
+        for (i64 y = (ylo / k) * k; y <= yhi; ++y) {
+            rp = (y % k == 0) ? src[y * I] : Op::apply(rp, src[y * I]);
+            const i64 x = y - k + 1;
+            if (x >= x0 && x < x1 && x % k != 0) dst[x * I] = Op::apply(dst[x * I], rp);
+        }
+    }
+    const i64 lb = (n - 1) / k, ls = lb * k;
+    if (lb >= 1) {
+        const i64 lo = ls - k + 1 > n - k + 1 ? ls - k + 1 : n - k + 1;
+        const i64 a = x0 > lo ? x0 : lo, b = x1 < ls ? x1 : ls;
+        if (a < b) {
+            T rpl = e;
+            for (i64 y = ls; y < n; ++y) rpl = Op::apply(rpl, src[y * I]);
+            for (i64 x = a; x < b; ++x)
+                if (x % k != 0) dst[x * I] = Op::apply(dst[x * I], rpl);
+        }
+    }
+}
+
 template <typename T, class Op>
 __global__ __launch_bounds__(256) void k_ex1d_2sweep(const T* __restrict__ W,
                                                      const T* __restrict__ Trest,
@@ -594,6 +697,14 @@ template <typename T, class Op>
 void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st) {
     const int kb = bucket_for(k);
     if (kb == 0) {
+        const i64 ch = ex2_chunks(n, O * I);
+        if (ch > 1) {
+            KTimer timer("k_bdbs2c", st);
+            const i64 L = (n + ch - 1) / ch, C = (n + L - 1) / L;
+            hipLaunchKernelGGL((k_bdbs2c<T, Op>), dim3(grid_for(O * C * I)), dim3(256), 0, st,
+                               in, out, O, n, I, k, L, C);
+            return;
+        }
         KTimer timer("k_bdbs_2sweep", st);
         hipLaunchKernelGGL((k_bdbs_2sweep<T, Op>), dim3(grid_for(O * I)), dim3(256), 0, st,
                            in, out, O, n, I, k);
@@ -911,13 +1022,22 @@ void launch_segexp(const T* Gw, const T* SPX, const T* SSX, T* PX, T* SX, i64 Q,
 
 template <typename T, class Op>
 void launch_axis0(const T* W, const T* PX, const T* SX, const T* Trest, T* exc, T* inc, i64 n0,
-                  i64 M, i64 k0, i64 Q, hipStream_t st) {
+                  i64 M, i64 k0, i64 Q, T* ex2t, hipStream_t st) {
     const int kb = bucket_for(k0);
     if (kb == 0) {
-        KTimer timer("k_ex1d_2sweep", st);
-        if (exc)
+        const i64 ch = ex2_chunks(n0, M);
+        if (exc && ch > 1 && ex2t) {
+            KTimer timer("k_ex2c", st);
+            const i64 L = (n0 + ch - 1) / ch, C = (n0 + L - 1) / L;
+            hipLaunchKernelGGL((k_ex2c_tot<T, Op>), dim3(grid_for(C * M)), dim3(256), 0, st, W,
+                               ex2t, n0, M, L, C);
+            hipLaunchKernelGGL((k_ex2c_out<T, Op>), dim3(grid_for(C * M)), dim3(256), 0, st, W,
+                               Trest, (const T*)ex2t, exc, n0, M, k0, L, C);
+        } else if (exc) {
+            KTimer timer("k_ex1d_2sweep", st);
             hipLaunchKernelGGL((k_ex1d_2sweep<T, Op>), dim3(grid_for(M)), dim3(256), 0, st, W,
                                Trest, exc, n0, M, k0);
+        }
         if (inc) launch_bdbs<T, Op>(W, inc, 1, n0, M, k0, st);
         return;
     }
@@ -995,7 +1115,7 @@ void launch_fill(void* out, i64 count, int dtype, int kind, uint64_t seed, i64 l
     template void launch_blockscan<T, OP>(const T*, const T*, T*, T*, T*, i64, i64, i64,       \
                                           hipStream_t);                                        \
     template void launch_axis0<T, OP>(const T*, const T*, const T*, const T*, T*, T*, i64, i64, \
-                                      i64, i64, hipStream_t);
+                                      i64, i64, T*, hipStream_t);
 
 EXS_INSTANTIATE(float, OpSum)
 EXS_INSTANTIATE(double, OpSum)

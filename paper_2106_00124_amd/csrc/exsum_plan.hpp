@@ -408,9 +408,12 @@ static exs_status plan_job(const exs_job* job, Arena& ar, Sink& sink) {
             continue;
         }
         const T* W = filter_axes<T>(src, n + j, k + j, dj, 1, dj - 1, wb0, wb1, dry, sink);
+        // boxes longer than 64 with few points: chunk totals for the chunked sweep
+        const i64 ch = bucket_for(k[j]) == 0 && out ? ex2_chunks(n[j], M[j]) : 1;
+        T* ex2t = ch > 1 ? ar.take<T>(ch * M[j]) : nullptr;
         if (!dry)
             sink.axis0(W, PX[j], SX[j], Trest, out, j == 0 ? inc : nullptr, n[j], M[j], k[j],
-                       Q[j]);
+                       Q[j], ex2t);
     }
     return EXS_OK;
 }

@@ -327,3 +327,27 @@ def test_parity_small2d(orc, shape, box, dtype, op, mode):
     inc, exc = gpu_run(a, box, op, mode)
     compare_full(orc, a, box, op, dtype, inc if mode != "exc" else None,
                  exc if mode != "inc" else None, what=f"small2d {shape} {box} {mode}")
+
+
+# boxes longer than 64 with few columns: the sweeps in chunks of rows (chunks
+# shorter and longer than the box, a ragged last chunk, k = n, the excluded
+# part along axis 0 and BDBS along strided and contiguous axes)
+LONG_BOX = [
+    ((300, 50), (100, 3)),
+    ((4100, 3), (65, 3)),
+    ((1000, 7, 90), (130, 2, 70)),
+    ((200, 300), (7, 200)),
+    ((129, 130), (129, 130)),
+    ((70, 5000), (66, 1)),
+]
+
+
+@pytest.mark.parametrize("shape,box", LONG_BOX, ids=lambda v: "x".join(map(str, v)))
+@pytest.mark.parametrize("dtype,op", [("f32", "sum"), ("i32", "max"), ("f64", "min"),
+                                      ("i64", "sum")], ids=lambda v: str(v))
+def test_parity_long_box_chunked(orc, shape, box, dtype, op):
+    seed = seed_of(shape, box, dtype, op, "longbox")
+    say(f"[long-box] shape={shape} box={box} dtype={dtype} op={op} seed={seed}")
+    a = make_input(shape, dtype, seed=seed, op=op)
+    inc, exc = gpu_run(a, box, op, "both")
+    compare_full(orc, a, box, op, dtype, inc, exc, what=f"long-box {shape} {box}")
