@@ -124,8 +124,8 @@ void launch_blockscan(const T* Gw, const T* Ga, T* PX, T* SX, T* R, i64 Q, i64 M
 // plain per-column sweep), the axis-0 stream's needing C x M chunk totals of
 // workspace (ex2t)
 inline i64 ex2_chunks(i64 n, i64 cols) {
-    if (cols >= ((i64)1 << 18)) return 1;
-    i64 c = (((i64)1 << 19) + cols - 1) / cols;
+    if (cols >= ((i64)1 << 20)) return 1;
+    i64 c = (((i64)1 << 20) + cols - 1) / cols;
     const i64 cmax = (n + 63) / 64;  // chunks of at least 64 rows
     if (c > cmax) c = cmax;
     return c < 1 ? 1 : c;
