@@ -594,24 +594,16 @@ __global__ __launch_bounds__(256) void k_ex2c_out(const T* __restrict__ W,
     }
 }
 
-// BDBS for boxes longer than 64 along an axis of an (O, n, I) tensor in chunks
-// of L rows: thread (o, chunk, i) forms the range suffixes of its rows (a
-// backward walk from the end of the block holding its last row), then adds
-// the range prefix of the next block up to x + k - 1 (a forward walk from the
-// start of the block holding its first row + k - 1), and for the windows
-// whose next block is the partial last block, that block's whole op.
+// BDBS for boxes longer than 64 along an axis, rows x0 .. x1 - 1 of one
+// column (stride I): the range suffixes of its rows (a backward walk from the
+// end of the block holding its last row), then the range prefix of the next
+// block up to x + k - 1 added (a forward walk from the start of the block
+// holding its first row + k - 1), and for the windows whose next block is the
+// partial last block, that block's whole op.
 template <typename T, class Op>
-__global__ __launch_bounds__(256) void k_bdbs2c(const T* __restrict__ in, T* __restrict__ out,
-                                                i64 O, i64 n, i64 I, i64 k, i64 L, i64 C) {
-    const i64 idx = gtid();
-    if (idx >= O * C * I) return;
+__device__ __forceinline__ void bdbs_long_chunk(const T* __restrict__ src, T* __restrict__ dst,
+                                                i64 I, i64 n, i64 k, i64 x0, i64 x1) {
     const T e = Op::template id<T>();
-    const i64 i = idx % I, rest = idx / I;
-    const i64 c = rest % C, o = rest / C;
-    const T* src = in + o * n * I + i;
-    T* dst = out + o * n * I + i;
-    const i64 x0 = c * L, x1 = x0 + L < n ? x0 + L : n;
-    if (x0 >= x1) return;
     const i64 bend = ((x1 - 1) / k + 1) * k < n ? ((x1 - 1) / k + 1) * k : n;
     T rs = e;
     for (i64 y = bend - 1; y >= x0; --y) {
@@ -640,6 +632,47 @@ __global__ __launch_bounds__(256) void k_bdbs2c(const T* __restrict__ in, T* __r
                 if (x % k != 0) dst[x * I] = Op::apply(dst[x * I], rpl);
         }
     }
+}
+
+// Boxes longer than 64 along an axis of an (O, n, I) tensor in chunks of L
+// rows, one thread per (o, chunk, i).
+template <typename T, class Op>
+__global__ __launch_bounds__(256) void k_bdbs2c(const T* __restrict__ in, T* __restrict__ out,
+                                                i64 O, i64 n, i64 I, i64 k, i64 L, i64 C) {
+    const i64 idx = gtid();
+    if (idx >= O * C * I) return;
+    const i64 i = idx % I, rest = idx / I;
+    const i64 c = rest % C, o = rest / C;
+    const i64 x0 = c * L, x1 = x0 + L < n ? x0 + L : n;
+    if (x0 >= x1) return;
+    bdbs_long_chunk<T, Op>(in + o * n * I + i, out + o * n * I + i, I, n, k, x0, x1);
+}
+
+// The same along the contiguous axis: a workgroup stages R whole rows in LDS
+// with coalesced loads, its threads take the (row, chunk) walks there, and the
+// rows go back with coalesced stores (walking a row in global memory per
+// thread leaves a wavefront's loads a row apart).
+template <typename T, class Op>
+__global__ __launch_bounds__(256) void k_bdbs2c_rows(const T* __restrict__ in,
+                                                     T* __restrict__ out, i64 O, int n, int k,
+                                                     int R, int L, int C) {
+    extern __shared__ __align__(16) unsigned char exs_l2c[];
+    T* sin = (T*)exs_l2c;
+    T* sout = sin + (i64)R * n;
+    const i64 o0 = (i64)blockIdx.x * R;
+    const int rows = O - o0 < R ? (int)(O - o0) : R;
+    const T* g = in + o0 * n;
+    for (int i = threadIdx.x; i < rows * n; i += 256) sin[i] = g[i];
+    __syncthreads();
+    for (int t = threadIdx.x; t < rows * C; t += 256) {
+        const int r = t / C, c = t - r * C;
+        const int x0 = c * L, x1 = x0 + L < n ? x0 + L : n;
+        if (x0 < x1)
+            bdbs_long_chunk<T, Op>(sin + (i64)r * n, sout + (i64)r * n, 1, n, k, x0, x1);
+    }
+    __syncthreads();
+    T* h = out + o0 * n;
+    for (int i = threadIdx.x; i < rows * n; i += 256) h[i] = sout[i];
 }
 
 template <typename T, class Op>
@@ -697,6 +730,19 @@ template <typename T, class Op>
 void launch_bdbs(const T* in, T* out, i64 O, i64 n, i64 I, i64 k, hipStream_t st) {
     const int kb = bucket_for(k);
     if (kb == 0) {
+        if (I == 1 && 2 * n * (i64)sizeof(T) <= 65536) {
+            // rows staged in LDS: R rows per workgroup, about 256 walks each
+            KTimer timer("k_bdbs2c_rows", st);
+            const int R = (int)(65536 / (2 * n * (i64)sizeof(T)) < 64 ? 65536 / (2 * n * (i64)sizeof(T)) : 64);
+            int C = (256 + R - 1) / R;
+            if (C > n) C = (int)n;
+            const int L = (int)((n + C - 1) / C);
+            C = (int)((n + L - 1) / L);
+            const size_t lds = 2 * (size_t)R * (size_t)n * sizeof(T);
+            hipLaunchKernelGGL((k_bdbs2c_rows<T, Op>), dim3((unsigned)((O + R - 1) / R)), dim3(256),
+                               lds, st, in, out, O, (int)n, (int)k, R, L, C);
+            return;
+        }
         const i64 ch = ex2_chunks(n, O * I);
         if (ch > 1) {
             KTimer timer("k_bdbs2c", st);
